@@ -1,0 +1,287 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle itself.
+
+Each test names the passage of arXiv 2301.04249 it checks.  The GPU path is
+not involved; these run on the CPU only.
+"""
+import itertools
+import os
+
+import numpy as np
+import pytest
+
+from oracle import ccsd, fockspace, memory, propagate, reference
+from synthetic import Shape, draw_system
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _system(o, v, q, cfg, scale, na=None, nb=None, core=(0, 1)):
+    eps, chol = draw_system(Shape(o, v, q), cfg=cfg, chol_scale=scale)
+    na = o if na is None else na
+    nb = o if nb is None else nb
+    return reference.n_minus_one_reference(eps, chol, na, nb, core[0], core[1])
+
+
+def _random_amplitudes(sys, seed, scale=0.1):
+    rng = np.random.default_rng(seed)
+    no, nv = sys.no, sys.nv
+    t1 = (rng.standard_normal((no, nv)) + 1j * rng.standard_normal((no, nv))) * scale
+    t2 = (rng.standard_normal((no, no, nv, nv)) + 1j * rng.standard_normal((no, no, nv, nv))) * scale
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    # zero the amplitudes that spin symmetry forbids (their residual is zero too)
+    spin = lambda idx: idx // sys.n  # noqa: E731
+    so, sv = spin(sys.occ), spin(sys.vir)
+    t1 = t1 * (so[:, None] == sv[None, :])
+    allowed = ((so[:, None, None, None] + so[None, :, None, None])
+               == (sv[None, None, :, None] + sv[None, None, None, :]))
+    same = ((so[:, None, None, None] == sv[None, None, :, None]) & (so[None, :, None, None] == sv[None, None, None, :])) | \
+           ((so[:, None, None, None] == sv[None, None, None, :]) & (so[None, :, None, None] == sv[None, None, :, None]))
+    t2 = t2 * (allowed & same)
+    return t1, t2
+
+
+# ---------------------------------------------------------------- P1 ----------
+@pytest.mark.parametrize("case", [
+    dict(o=3, v=3, na=3, nb=3, core=(0, 1)),   # closed-shell N, beta core hole
+    dict(o=3, v=3, na=3, nb=2, core=(1, 0)),   # open-shell N, alpha hole
+    dict(o=3, v=3, na=2, nb=3, core=(0, 1)),
+])
+def test_residual_and_energy_match_determinant_space(case):
+    """Eqs. dt1eom/dt2eom and cum_gf3: projections of e^{-T} H_N e^{T} by brute force.
+
+    Random complex T1 and T2 with a non-canonical (N-1) Fock matrix exercise
+    every term of the closed-form residual; a dropped term, a wrong sign or a
+    swapped index changes R by O(1) against the 1e-12 tolerance.
+    """
+    sys = _system(case["o"], case["v"], 10, cfg=99, scale=3.0, na=case["na"], nb=case["nb"],
+                  core=case["core"])
+    assert np.abs(sys.fblock("ov")).max() > 1e-3   # f_ia != 0: non-HF reference
+    t1, t2 = _random_amplitudes(sys, seed=5)
+    r1b, r2b, eb = fockspace.projections(sys, t1, t2)
+    r1, r2 = ccsd.residual(sys, t1, t2)
+    e = ccsd.energy(sys, t1, t2)
+    assert np.abs(r1 - r1b).max() < 1e-12 * max(1.0, np.abs(r1b).max())
+    assert np.abs(r2 - r2b).max() < 1e-12 * max(1.0, np.abs(r2b).max())
+    assert abs(e - eb) < 1e-12
+    assert np.abs(r2b).max() > 1.0 and np.abs(r1b).max() > 0.5
+
+
+def test_residual_brute_force_unconstrained_amplitudes():
+    """The projection is linear-algebra exact for any T, including spin-forbidden entries."""
+    sys = _system(2, 3, 8, cfg=97, scale=3.0)
+    rng = np.random.default_rng(11)
+    no, nv = sys.no, sys.nv
+    t1 = (rng.standard_normal((no, nv)) + 1j * rng.standard_normal((no, nv))) * 0.2
+    t2 = (rng.standard_normal((no, no, nv, nv)) + 1j * rng.standard_normal((no, no, nv, nv))) * 0.2
+    t2 = t2 - t2.transpose(1, 0, 2, 3)
+    t2 = t2 - t2.transpose(0, 1, 3, 2)
+    r1b, r2b, eb = fockspace.projections(sys, t1, t2)
+    r1, r2 = ccsd.residual(sys, t1, t2)
+    assert np.abs(r1 - r1b).max() < 1e-12 * np.abs(r1b).max()
+    assert np.abs(r2 - r2b).max() < 1e-12 * np.abs(r2b).max()
+    assert abs(ccsd.energy(sys, t1, t2) - eb) < 1e-12
+
+
+# ---------------------------------------------------------------- P2 ----------
+def test_cholesky_integrals_against_explicit_loops():
+    """Sec. 2.3: (pq|rs) = sum_Q L^Q_pq L^Q_rs; spin-orbital <pq||rs> by explicit loops."""
+    eps, chol = draw_system(Shape(2, 2, 5), cfg=3)
+    n = eps.size
+    eri = reference.coulomb_from_cholesky(chol)
+    g = reference.antisymmetrized_spin_orbital(eri)
+    for p, q, r, s in itertools.product(range(2 * n), repeat=4):
+        sp, sq, sr, ss = p // n, q // n, r // n, s // n
+        P, Q, R, S = p % n, q % n, r % n, s % n
+        direct = sum(chol[k, P, R] * chol[k, Q, S] for k in range(chol.shape[0])) if (sp == sr and sq == ss) else 0.0
+        exch = sum(chol[k, P, S] * chol[k, Q, R] for k in range(chol.shape[0])) if (sp == ss and sq == sr) else 0.0
+        assert abs(g[p, q, r, s] - (direct - exch)) < 1e-14
+    # eight-fold permutational symmetry of real (pq|rs)
+    assert np.allclose(eri, eri.transpose(1, 0, 2, 3))
+    assert np.allclose(eri, eri.transpose(2, 3, 0, 1))
+
+
+def test_fock_of_n_minus_one_reference():
+    """f_pq = eps_p delta_pq - <pc||qc>; for the opposite spin of c only the Coulomb part survives."""
+    eps, chol = draw_system(Shape(3, 4, 9), cfg=4)
+    n = eps.size
+    sys = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    eri = reference.coulomb_from_cholesky(chol)
+    fa = sys.fock[:n, :n]
+    fb = sys.fock[n:, n:]
+    assert np.allclose(fa, np.diag(eps) - eri[:, :, 0, 0], atol=1e-14)
+    assert np.allclose(fb, np.diag(eps) - eri[:, :, 0, 0] + eri[:, 0, 0, :], atol=1e-14)
+    assert np.abs(sys.fock[:n, n:]).max() == 0.0
+    assert n in sys.vir and n not in sys.occ        # beta core orbital joined the virtuals
+
+
+# ---------------------------------------------------------------- P4 ----------
+def test_initial_conditions_and_antisymmetry():
+    """Sec. 3: T1 = T2 = 0 at tau = 0, so E = 0 and C(0) = 0; R(0) = (f_ia, <ij||ab>)."""
+    sys = _system(3, 5, 12, cfg=0, scale=1.0)
+    t1, t2 = ccsd.zero_amplitudes(sys)
+    r1, r2 = ccsd.residual(sys, t1, t2)
+    assert np.array_equal(r1, sys.fblock("ov"))
+    assert np.array_equal(r2, sys.block("oovv"))
+    assert ccsd.energy(sys, t1, t2) == 0
+    tr = propagate.propagate(sys, 0.01, 3, tol=1e-12)
+    assert tr.cumulant[0] == 0
+    t2n = tr.t2
+    assert np.abs(t2n + t2n.transpose(1, 0, 2, 3)).max() < 1e-15
+    assert np.abs(t2n + t2n.transpose(0, 1, 3, 2)).max() < 1e-15
+    ta, tb = _random_amplitudes(sys, 3)
+    _, r2 = ccsd.residual(sys, ta, tb)
+    assert np.abs(r2 + r2.transpose(1, 0, 2, 3)).max() < 1e-13
+    assert np.abs(r2 + r2.transpose(0, 1, 3, 2)).max() < 1e-13
+
+
+# ---------------------------------------------------------------- P5 ----------
+def test_short_time_closed_form():
+    """C(tau) = -(tau^2/2) <Phi|H_N^2|Phi> + O(tau^3) (Eq. cum_gf3 with T ~ i tau R(0)).
+
+    <Phi|H_N^2|Phi> = sum |f_ia|^2 + 1/4 sum <ij||ab>^2, independent of the oracle's residual.
+    """
+    sys = _system(3, 6, 12, cfg=0, scale=1.0)
+    s = np.sum(sys.fblock("ov") ** 2) + 0.25 * np.sum(sys.block("oovv") ** 2)
+    ratios = []
+    for dt in (1e-3, 5e-4, 2.5e-4):
+        tr = propagate.propagate(sys, dt, 1, tol=1e-14, max_iter=100)
+        ratios.append(tr.cumulant[1] / (-0.5 * dt * dt * s))
+    dev = [abs(r - 1) for r in ratios]
+    assert dev[-1] < 1e-2
+    assert dev[0] / dev[1] > 1.8 and dev[1] / dev[2] > 1.8   # O(dt) relative correction
+
+
+def test_short_time_hn_squared_brute_force():
+    """The S of the closed form equals <Phi|H_N^2|Phi> from the determinant-space Hamiltonian."""
+    sys = _system(2, 3, 8, cfg=1, scale=2.0)
+    sector = fockspace.Sector(sys.nso, sys.no)
+    H = fockspace.hamiltonian(sys, sector)
+    k = sector.index[fockspace.reference_det(sys)]
+    HN = H - H[k, k] * np.eye(sector.dim)
+    s_brute = (HN @ HN)[k, k]
+    s = np.sum(sys.fblock("ov") ** 2) + 0.25 * np.sum(sys.block("oovv") ** 2)
+    assert abs(s - s_brute) < 1e-12 * s_brute
+
+
+# ---------------------------------------------------------------- P6 ----------
+@pytest.mark.parametrize("occ", [(2, 1, 0, 0), (3, 0, 1, 0)])
+def test_two_electron_exactness(occ):
+    """With two electrons CCSD is full CI: e^{C(tau)} = <Phi|e^{i H_N tau}|Phi> up to O(dt^2).
+
+    Exact diagonalisation of H in the two-electron sector supplies the reference
+    (Eqs. N_c, cum_gf3: N_c = e^{i E_ref tau} e^{C}).
+    """
+    na, nb, co, cs = occ
+    eps, chol = draw_system(Shape(2, 4, 12), cfg=98, chol_scale=3.0)
+    sys = reference.n_minus_one_reference(eps, chol, na, nb, co, cs)
+    assert sys.no == 2
+    tau = 0.5
+    errs = []
+    cs_ = []
+    for dt in (0.01, 0.005, 0.0025):
+        n = int(round(tau / dt))
+        tr = propagate.propagate(sys, dt, n, tol=1e-12, max_iter=200)
+        ex = fockspace.exact_overlap(sys, tr.times)
+        errs.append(abs(np.exp(tr.cumulant[-1]) - ex[-1]))
+        cs_.append(np.exp(tr.cumulant[-1]))
+    assert errs[0] / errs[1] > 3.5 and errs[1] / errs[2] > 3.5
+    richardson = (4 * cs_[2] - cs_[1]) / 3
+    assert abs(richardson - ex[-1]) < 0.05 * errs[2]
+
+
+# ---------------------------------------------------------------- P7 ----------
+def test_spin_flip_invariance():
+    """A closed-shell N reference: a core hole in alpha or in beta gives the same C(t)."""
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    a = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 0)
+    b = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    ta = propagate.propagate(a, 0.025, 8, fixed_iters=4)
+    tb = propagate.propagate(b, 0.025, 8, fixed_iters=4)
+    assert np.abs(ta.cumulant - tb.cumulant).max() < 1e-13
+    assert np.abs(ta.cumulant).max() > 1e-3
+
+
+# ---------------------------------------------------------------- P8 ----------
+def test_integrator_order():
+    """Eq. trapzrule: observed convergence order of C(tau) is >= 0.9 (the trapezoid gives ~2)."""
+    sys = _system(2, 4, 10, cfg=0, scale=1.0)
+    tau = 0.32
+    ref = propagate.propagate(sys, 0.04 / 64, 64 * 8, tol=1e-13, max_iter=100).cumulant[-1]
+    errs = []
+    for k in (1, 2, 4):
+        dt = 0.04 / k
+        c = propagate.propagate(sys, dt, 8 * k, tol=1e-13, max_iter=100).cumulant[-1]
+        errs.append(abs(c - ref))
+    p1 = np.log2(errs[0] / errs[1])
+    p2 = np.log2(errs[1] / errs[2])
+    assert p1 > 0.9 and p2 > 0.9
+    assert 1.7 < p2 < 2.3
+    del tau
+
+
+# ---------------------------------------------------------------- P9 ----------
+def test_fixed_point_maps_agree():
+    """The plain and the denominator map share the fixed point of Eq. trapzrule."""
+    sys = _system(3, 5, 12, cfg=0, scale=1.0)
+    t1, t2 = _random_amplitudes(sys, 7, scale=0.01)
+    a1, a2, _ = propagate.trapezoid_step(sys, t1, t2, 0.02, tol=1e-14, max_iter=200, fp_map="plain")
+    b1, b2, _ = propagate.trapezoid_step(sys, t1, t2, 0.02, tol=1e-14, max_iter=200, fp_map="denominator")
+    assert np.abs(a1 - b1).max() < 1e-12
+    assert np.abs(a2 - b2).max() < 1e-12
+    # and both satisfy the implicit equation itself
+    h = 0.01j
+    r0 = ccsd.residual(sys, t1, t2)
+    r1 = ccsd.residual(sys, a1, a2)
+    assert np.abs(a2 - (t2 + h * (r0[1] + r1[1]))).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P10 ---------
+def test_table2_t2_memory():
+    """Table 2, T2 column: full aa+bb+ab complex128 blocks in GiB per timeline tensor."""
+    rows = []
+    with open(os.path.join(GOLDEN, "table2_t2_memory.txt")) as fh:
+        for line in fh:
+            if line.startswith("#") or not line.strip():
+                continue
+            name, oa, ob, va, vb, gb = line.split()
+            rows.append((name, int(oa), int(ob), int(va), int(vb), float(gb)))
+    assert len(rows) == 4
+    for name, oa, ob, va, vb, gb in rows:
+        assert abs(memory.t2_gib(oa, ob, va, vb) - gb) < 0.1, name
+
+
+# ---------------------------------------------------------------- P11 ---------
+def test_noninteracting_limit():
+    """L = 0: f = diag(eps), R(T) = -D*T, so T stays 0 and C stays 0 (Fock definition, Sec. 2.1)."""
+    eps, chol = draw_system(Shape(3, 4, 6), cfg=0)
+    sys = reference.n_minus_one_reference(eps, 0 * chol, 3, 3, 0, 1)
+    assert np.array_equal(sys.fock, np.diag(np.concatenate([eps, eps])))
+    tr = propagate.propagate(sys, 0.05, 5, fixed_iters=3)
+    assert np.abs(tr.cumulant).max() == 0.0
+    t1, t2 = _random_amplitudes(sys, 1)
+    r1, r2 = ccsd.residual(sys, t1, t2)
+    d1, d2 = propagate._denominators(sys)
+    assert np.abs(r1 + d1 * t1).max() < 1e-14
+    assert np.abs(r2 + d2 * t2).max() < 1e-14
+
+
+def test_energy_fT1_reading():
+    """Eq. cum_gf3 vs the printed Eq. dcdt: they differ by exactly sum_ia f_ia t_ia."""
+    sys = _system(3, 5, 12, cfg=0, scale=1.0)
+    t1, t2 = _random_amplitudes(sys, 9)
+    d = ccsd.energy(sys, t1, t2, True) - ccsd.energy(sys, t1, t2, False)
+    assert abs(d - np.sum(sys.fblock("ov") * t1)) < 1e-14
+
+
+def test_green_function_and_spectrum_free_particle():
+    """C = 0: G = -i e^{-i eps_c tau}; A(omega) is a Lorentzian of width eta at eps_c (Eq. cum_gf)."""
+    times = np.arange(0, 4000) * 0.05
+    g = propagate.green_function(times, np.zeros_like(times, dtype=complex), -20.0)
+    omegas = np.linspace(-20.5, -19.5, 1001)
+    eta = 0.05
+    a = propagate.spectral_function(times, g, omegas, eta)
+    peak = propagate.qp_peak(omegas, a)
+    assert abs(peak - (-20.0)) < 1e-4
+    lorentz = eta / np.pi / ((omegas + 20.0) ** 2 + eta ** 2)
+    assert np.abs(a - lorentz).max() < 2e-2 * lorentz.max()

@@ -1,0 +1,149 @@
+/*
+ * rteom.h -- C ABI of the MI355X RT-EOM-CCSD hot path (arXiv 2301.04249).
+ *
+ * The library propagates the complex CCSD amplitudes of a core-ionised
+ * (N-1)-electron reference in time and accumulates the cumulant C(t):
+ *
+ *   -i dt_x/dtau = <Phi_x|(H_N e^{T1+T2})_C|Phi>          (Eqs. dt1eom, dt2eom)
+ *   T(tau+dt) = T(tau) + (i dt/2)[R(T(tau)) + R(T(tau+dt))] (Eq. trapzrule)
+ *   C(tau) = i int_0^tau <Phi|(H_N e^{T})_C|Phi> dtau'      (Eq. cum_gf3)
+ *
+ * with the two-electron integrals Cholesky factorised,
+ * (pq|rs) = sum_Q L^Q_pq L^Q_rs (Sec. 2.3), spin-explicit (alpha-alpha,
+ * alpha-beta, beta-beta) amplitude blocks, and the (N-1) Fock matrix
+ * f_pq = eps_p delta_pq - <pc||qc> (Sec. 2.1).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every function returns rteom_status (0 = RTEOM_OK).  Nothing aborts and no
+ *   C++ exception crosses the ABI; rteom_last_error() gives a message.
+ * - Pointers named "host" are CPU memory owned by the caller; they are read or
+ *   written during the call only.  Device memory is either the caller's
+ *   workspace (rteom_options.workspace, e.g. a torch tensor) or allocated by
+ *   the library when that pointer is NULL; rteom_free releases what the
+ *   library allocated and never the caller's workspace.
+ * - Work is ordered on rteom_options.stream (a hipStream_t, NULL = the null
+ *   stream).  Calls that return host data synchronise that stream.
+ * - Orbital spaces: the N-electron determinant occupies spatial orbitals
+ *   0..n_occ_a-1 (alpha) and 0..n_occ_b-1 (beta); the core spin-orbital
+ *   (core_orb, core_spin) is removed to make |Phi>.  The library works in an
+ *   "extended" space: O = orbitals occupied in Phi in either spin (ascending),
+ *   V = orbitals virtual in Phi in either spin (ascending), n_o = |O|,
+ *   n_v = |V|.  Amplitudes of a spin that does not exist (e.g. beta
+ *   amplitudes with i = core) are identically zero.
+ * - Host amplitude layout (rteom_set_amplitudes / get / residual): complex
+ *   numbers as interleaved (re, im) doubles;
+ *     t1: [2 spins][n_o][n_v]                     (alpha, beta)
+ *     t2: [3 blocks][n_o][n_o][n_v][n_v]          (aa, ab, bb)
+ *   t1[s][i][a] = t_{i s}^{a s};  t2[aa][i][j][a][b] = t_{i a, j a}^{a a, b a}
+ *   (antisymmetric in i,j and in a,b), t2[ab][i][j][a][b] =
+ *   t_{i alpha, j beta}^{a alpha, b beta}, t2[bb] like aa for beta.
+ */
+#ifndef RTEOM_H
+#define RTEOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rteom_ctx rteom_ctx;
+
+typedef enum {
+  RTEOM_OK = 0,
+  RTEOM_ERR_ARG = 1,        /* invalid argument (sizes, indices, dt, options) */
+  RTEOM_ERR_OOM = 2,        /* workspace too small or device allocation failed */
+  RTEOM_ERR_HIP = 3,        /* a HIP runtime call failed */
+  RTEOM_ERR_NOCONV = 4,     /* fixed point not converged; the step is not committed */
+  RTEOM_ERR_NONFINITE = 5,  /* NaN/Inf in the inputs or in the amplitudes */
+  RTEOM_ERR_STATE = 6       /* call not valid in the context's current state */
+} rteom_status;
+
+typedef enum {
+  RTEOM_FP64 = 0,   /* contractions in float64 (MFMA f64) */
+  RTEOM_FP32 = 1,   /* contractions in float32 (MFMA f32), float64 storage */
+  RTEOM_BF16X3 = 2  /* bf16 hi/lo split, three MFMA products, float32 accumulation */
+} rteom_prec;
+
+typedef struct {
+  uint32_t struct_size;    /* must be sizeof(rteom_options) */
+  int32_t prec;            /* rteom_prec of the contractions; update and C(t) stay float64 */
+  int32_t fp_map;          /* 0: plain fixed point of Eq. trapzrule; 1: diagonal ("denominator") map */
+  int32_t fp_fixed_iters;  /* > 0: exactly this many corrector passes per step (no convergence test) */
+  int32_t fp_max_iter;     /* pass limit when tolerance driven */
+  double fp_tol;           /* max |T^(k+1) - T^(k)| over all amplitudes that ends the passes */
+  int32_t dC_include_fT1;  /* 1: dC/dt includes sum f_ia t_ia (Eq. cum_gf3); 0: Eq. dcdt as printed */
+  int32_t reserved0;
+  int64_t max_steps;       /* capacity of the device C(t) history (time steps) */
+  void* stream;            /* hipStream_t borrowed from the caller; NULL = null stream */
+  void* workspace;         /* caller-owned device memory, or NULL (library allocates) */
+  size_t workspace_bytes;  /* size of workspace */
+} rteom_options;
+
+/* Fill *opt with defaults: FP64, plain map, tolerance 1e-10, 50 passes,
+   dC_include_fT1 = 1, max_steps = 100000, null stream, no workspace. */
+void rteom_default_options(rteom_options* opt);
+
+/* Device bytes rteom_init needs for these sizes and options (no GPU work). */
+rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
+                                   int32_t n_chol, int32_t core_orb, int32_t core_spin,
+                                   const rteom_options* opt, size_t* bytes);
+
+/* Create a propagation context (Sec. 3, the time-dependent simulation of one core hole).
+   fock_diag: host [n_orb], the N-electron orbital energies eps_p (Fock diagonal).
+   chol:      host [n_chol][n_orb][n_orb], Cholesky vectors L^Q_pq, symmetric in (p,q).
+   core_orb/core_spin: the ionised spin-orbital c (spatial index occupied in that spin,
+   0 = alpha, 1 = beta).  Builds the (N-1) Fock matrix and the integral blocks on the
+   device; T(0) = 0 and C(0) = 0.  The caller may free the host arrays afterwards.
+   Errors: ARG (sizes, indices, non-symmetric L), NONFINITE, OOM, HIP. */
+rteom_status rteom_init(rteom_ctx** ctx, int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
+                        const double* fock_diag, int32_t n_chol, const double* chol,
+                        int32_t core_orb, int32_t core_spin, const rteom_options* opt);
+
+/* Advance n_steps time steps of length dt (Eq. trapzrule with fixed-point passes) and
+   append C(t) for each.  micro_iters_out (nullable, host [n_steps]) receives the passes
+   used per step.  NOCONV leaves the amplitudes and C(t) at the last committed step. */
+rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* micro_iters_out);
+
+/* Copy the cumulant history to host: t_out [cap] times, c_out [cap][2] (re, im) of
+   C(t_0 = 0) ... C(t_n); *n_out = number written (steps taken + 1, at most cap).
+   cap = 0 is a length query: nothing is written and *n_out = steps taken + 1. */
+rteom_status rteom_cumulant(const rteom_ctx* ctx, int64_t cap, double* t_out, double* c_out,
+                            int64_t* n_out);
+
+/* Extended-space sizes and orbital lists: occ_list [n_o], vir_list [n_v] (nullable). */
+rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_t* occ_list,
+                        int32_t* vir_list);
+
+/* Replace the current amplitudes (host layout above).  Entries of non-existent spin
+   amplitudes are ignored (set to zero).  Test and benchmark hook. */
+rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double* t2);
+
+/* Copy the current amplitudes to host (layout above). */
+rteom_status rteom_get_amplitudes(const rteom_ctx* ctx, double* t1, double* t2);
+
+/* One residual evaluation R(T) = <Phi_x|e^{-T} H_N e^{T}|Phi> at the current amplitudes
+   (Eqs. dt1eom, dt2eom).  r1_out/r2_out: host, amplitude layout; either may be NULL
+   (the residual is still computed, e.g. for timing). */
+rteom_status rteom_residual(rteom_ctx* ctx, double* r1_out, double* r2_out);
+
+/* <Phi|(H_N e^T)_C|Phi> at the current amplitudes (Eq. cum_gf3), e_out = (re, im). */
+rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
+
+/* Floating-point operations of one residual evaluation as this implementation performs
+   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex). */
+rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
+
+/* Release the context (NULL-safe). */
+rteom_status rteom_free(rteom_ctx* ctx);
+
+/* Last error message of this context (or of the last failed rteom_init when ctx is NULL). */
+const char* rteom_last_error(const rteom_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RTEOM_H */

@@ -1,0 +1,114 @@
+// Device operations used by the RT-EOM-CCSD engine.
+//
+// The engine (engine.cpp) expresses one residual evaluation and one time step
+// as a sequence of these operations; backend_hip.hip implements them with
+// hand-written gfx950 kernels.  Complex tensors are planar: a real plane and an
+// imaginary plane with identical strides.
+#pragma once
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+namespace rteom {
+
+constexpr int kMaxDims = 6;
+
+// C[b](m, n) = alpha * sum_k A[b](m, k) * B[b](k, n) + beta * C[b](m, n)
+// Each operand element is at base + b*sb + i*s0 + j*s1.  An operand whose
+// imaginary pointer is null is real.  C is real exactly when A and B are real.
+struct GemmOp {
+  int64_t M = 0, N = 0, K = 0, batch = 1;
+  const double* a_re = nullptr; const double* a_im = nullptr; int64_t a_sm = 0, a_sk = 0, a_sb = 0;
+  const double* b_re = nullptr; const double* b_im = nullptr; int64_t b_sk = 0, b_sn = 0, b_sb = 0;
+  double* c_re = nullptr; double* c_im = nullptr; int64_t c_sm = 0, c_sn = 0, c_sb = 0;
+  double alpha = 1.0;
+  int beta = 0;      // 0 overwrite, 1 accumulate
+  int prec = 0;      // rteom_prec
+};
+
+// out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an
+// nd-dimensional index space; strides per operand.  in may be real while out is
+// complex (then alpha may be complex).  in == out with beta = 0 scales in place.
+struct PermOp {
+  int nd = 0;
+  int64_t dim[kMaxDims] = {0};
+  const double* in_re = nullptr; const double* in_im = nullptr; int64_t in_str[kMaxDims] = {0};
+  double* out_re = nullptr; double* out_im = nullptr; int64_t out_str[kMaxDims] = {0};
+  const double* scale[kMaxDims] = {nullptr};  // optional real vector per dimension
+  double alpha_re = 1.0, alpha_im = 0.0;
+  int beta = 0;
+};
+
+// Layout of an amplitude set (t1 alpha, t1 beta, t2 aa, t2 ab, t2 bb), planar.
+struct AmpLayout {
+  int64_t no = 0, nv = 0;
+  int64_t n1() const { return no * nv; }
+  int64_t n2() const { return no * no * nv * nv; }
+  int64_t size() const { return 2 * n1() + 3 * n2(); }
+};
+
+// Per-spin occupancy masks and Fock diagonals (device vectors), used to zero
+// amplitudes of non-existent spin-orbitals and by the diagonal map.
+struct SpinVectors {
+  const double* mo[2] = {nullptr, nullptr};  // [no]
+  const double* mv[2] = {nullptr, nullptr};  // [nv]
+  const double* fo[2] = {nullptr, nullptr};  // [no] f_ii
+  const double* fv[2] = {nullptr, nullptr};  // [nv] f_aa
+};
+
+// Fused amplitude update of Eq. trapzrule (see engine.cpp, step()):
+//   start: rhs = x + i h r; then for every amplitude
+//   plain:       x' = rhs + i h r
+//   denominator: x' = (rhs + i h (r + D x)) / (1 + i h D)
+//   x' = 0 where the spin-orbital does not exist;  *delta = max |x' - x|.
+struct UpdateOp {
+  AmpLayout lay;
+  double* x_re = nullptr; double* x_im = nullptr;
+  const double* r_re = nullptr; const double* r_im = nullptr;
+  double* rhs_re = nullptr; double* rhs_im = nullptr;
+  double h = 0.0;      // dt / 2
+  int mode = 0;        // 0 plain, 1 denominator
+  int start = 0;       // 1: write rhs from x and r first
+  SpinVectors sv;
+  double* delta = nullptr;  // device double, max-reduced (caller zeroes it)
+};
+
+// E(T) = sum f_ia t_ia + 1/4 sum <ij||ab> t_ijab + 1/2 sum <ij||ab> t_ia t_jb in
+// spin-blocked form; writes (re, im) to e_out (device).
+struct EnergyOp {
+  AmpLayout lay;
+  const double* x_re = nullptr; const double* x_im = nullptr;
+  const double* jov = nullptr;        // (ia|jb) as [i][a][j][b]
+  const double* fov[2] = {nullptr, nullptr};  // f^s_ia as [no][nv] (row stride fov_ld)
+  int64_t fov_ld = 0;
+  int include_ft1 = 1;
+  double* e_out = nullptr;
+  double* partial = nullptr;          // scratch, >= energy_partials() doubles
+};
+
+class Backend {
+ public:
+  virtual ~Backend() {}
+  virtual void* alloc(size_t bytes) = 0;
+  virtual void release(void* p) = 0;
+  virtual void h2d(void* dst, const void* src, size_t bytes) = 0;
+  virtual void d2h(void* dst, const void* src, size_t bytes) = 0;   // synchronous
+  virtual void d2d(void* dst, const void* src, size_t bytes) = 0;
+  virtual void fill(double* p, int64_t n, double v) = 0;
+  virtual void gemm(const GemmOp& op) = 0;
+  virtual void permute(const PermOp& op) = 0;
+  virtual void update(const UpdateOp& op) = 0;
+  virtual void energy(const EnergyOp& op) = 0;
+  // C[k+1] = C[k] + i h (E_k + E_{k+1}); e_prev/e_next/c are device (re, im) pairs
+  virtual void cumulant_append(double* c_hist, int64_t k, const double* e_prev,
+                               const double* e_next, double h) = 0;
+  virtual int64_t energy_partials() const = 0;
+  virtual void sync() = 0;
+  // returns false (and a message) if an asynchronous error has been recorded
+  virtual bool ok(std::string* msg) = 0;
+};
+
+Backend* make_hip_backend(void* stream, std::string* err);
+
+}  // namespace rteom

@@ -1,0 +1,533 @@
+// gfx950 (MI355X) kernels of the RT-EOM-CCSD engine and the HIP backend.
+//
+//  gemm_f64   complex/real GEMM on the f64 matrix cores
+//             (v_mfma_f64_16x16x4f64), 64x64 output tile per 256-thread
+//             workgroup, operands staged through LDS.  Complex operands are
+//             planar; a complex x complex product is four real MFMA products
+//             per fragment, complex x real two.
+//  permute    strided tensor copy / accumulate / scale (HBM bound).
+//  update     fused trapezoid update of all amplitudes with the per-spin masks,
+//             the optional diagonal map and a max-|change| reduction.
+//  energy     <Phi|(H_N e^T)_C|Phi> as a two-pass deterministic reduction.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+
+#include "backend.h"
+
+namespace rteom {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int kThreads = 256;
+
+struct GemmArgs {
+  int64_t M, N, K, batch;
+  const double* ar; const double* ai; int64_t asm_, ask, asb;
+  const double* br; const double* bi; int64_t bsk, bsn, bsb;
+  double* cr; double* ci; int64_t csm, csn, csb;
+  double alpha;
+  int beta;
+  int64_t tiles_m, tiles_n;
+};
+
+// A tile [BK][BM] and B tile [BK][BN] in LDS (k-major) so that the MFMA
+// fragment reads (row = lane % 16, k = lane / 16) are unit stride across lanes.
+template <bool AC, bool BC, bool AKC, bool BKC>
+__global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
+  __shared__ double sa_r[BK][BM + PAD];
+  __shared__ double sa_i[AC ? BK : 1][BM + PAD];
+  __shared__ double sb_r[BK][BN + PAD];
+  __shared__ double sb_i[BC ? BK : 1][BN + PAD];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t tile = blockIdx.x;
+  const int64_t tm = tile / g.tiles_n, tn = tile % g.tiles_n;
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+
+  for (int64_t b = blockIdx.y; b < g.batch; b += gridDim.y) {
+    const double* Ar = g.ar + b * g.asb;
+    const double* Ai = AC ? g.ai + b * g.asb : nullptr;
+    const double* Br = g.br + b * g.bsb;
+    const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
+    d4 accr[2][2], acci[2][2];
+    for (int x = 0; x < 2; ++x)
+      for (int y = 0; y < 2; ++y) {
+        accr[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        acci[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+      }
+    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
+      // ---- stage A
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int kk, mm;
+        if (AKC) { kk = tid & 15; mm = (tid >> 4) + 16 * r; }
+        else     { mm = tid & 63; kk = (tid >> 6) + 4 * r; }
+        const int64_t gm = m0 + mm, gk = k0 + kk;
+        double vr = 0.0, vi = 0.0;
+        if (gm < g.M && gk < g.K) {
+          const int64_t o = gm * g.asm_ + gk * g.ask;
+          vr = Ar[o];
+          if (AC) vi = Ai[o];
+        }
+        sa_r[kk][mm] = vr;
+        if (AC) sa_i[kk][mm] = vi;
+      }
+      // ---- stage B
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int kk, nn;
+        if (BKC) { kk = tid & 15; nn = (tid >> 4) + 16 * r; }
+        else     { nn = tid & 63; kk = (tid >> 6) + 4 * r; }
+        const int64_t gn = n0 + nn, gk = k0 + kk;
+        double vr = 0.0, vi = 0.0;
+        if (gn < g.N && gk < g.K) {
+          const int64_t o = gk * g.bsk + gn * g.bsn;
+          vr = Br[o];
+          if (BC) vi = Bi[o];
+        }
+        sb_r[kk][nn] = vr;
+        if (BC) sb_i[kk][nn] = vi;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int ks = 0; ks < BK / 4; ++ks) {
+        const int kr = ks * 4 + (lane >> 4);
+        double a_r[2], a_i[2], b_r[2], b_i[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          a_r[x] = sa_r[kr][wm * 32 + x * 16 + (lane & 15)];
+          a_i[x] = AC ? sa_i[kr][wm * 32 + x * 16 + (lane & 15)] : 0.0;
+          b_r[x] = sb_r[kr][wn * 32 + x * 16 + (lane & 15)];
+          b_i[x] = BC ? sb_i[kr][wn * 32 + x * 16 + (lane & 15)] : 0.0;
+        }
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+          for (int y = 0; y < 2; ++y) {
+            accr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_r[y], accr[x][y], 0, 0, 0);
+            if (AC && BC) {
+              accr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[x], b_i[y], accr[x][y], 0, 0, 0);
+              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_i[y], acci[x][y], 0, 0, 0);
+              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], acci[x][y], 0, 0, 0);
+            } else if (AC) {
+              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], acci[x][y], 0, 0, 0);
+            } else if (BC) {
+              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_i[y], acci[x][y], 0, 0, 0);
+            }
+          }
+      }
+      __syncthreads();
+    }
+    // ---- epilogue: lane holds C[4*(lane/16) + r][lane % 16] of each 16x16 block
+    double* Cr = g.cr + b * g.csb;
+    double* Ci = (AC || BC) ? g.ci + b * g.csb : nullptr;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = m0 + wm * 32 + x * 16 + 4 * (lane >> 4) + r;
+          const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
+          if (gm < g.M && gn < g.N) {
+            const int64_t o = gm * g.csm + gn * g.csn;
+            double vr = g.alpha * accr[x][y][r];
+            if (g.beta) vr += Cr[o];
+            Cr[o] = vr;
+            if (AC || BC) {
+              double vi = g.alpha * acci[x][y][r];
+              if (g.beta) vi += Ci[o];
+              Ci[o] = vi;
+            }
+          }
+        }
+  }
+}
+
+struct PermArgs {
+  int nd;
+  int64_t dim[kMaxDims];
+  int64_t istr[kMaxDims], ostr[kMaxDims];
+  const double* ir; const double* ii;
+  double* orr; double* oi;
+  const double* sc[kMaxDims];
+  double ar, ai;
+  int beta;
+  int64_t total;
+};
+
+__global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < p.total; t += stride) {
+    int64_t r = t, io = 0, oo = 0;
+    double s = 1.0;
+    for (int d = p.nd - 1; d >= 0; --d) {
+      const int64_t dd = p.dim[d];
+      const int64_t x = r % dd;
+      r /= dd;
+      io += x * p.istr[d];
+      oo += x * p.ostr[d];
+      if (p.sc[d]) s *= p.sc[d][x];
+    }
+    const double xr = p.ir[io];
+    const double xi = p.ii ? p.ii[io] : 0.0;
+    double vr = s * (p.ar * xr - p.ai * xi);
+    double vi = s * (p.ar * xi + p.ai * xr);
+    if (p.beta) {
+      vr += p.orr[oo];
+      if (p.oi) vi += p.oi[oo];
+    }
+    p.orr[oo] = vr;
+    if (p.oi) p.oi[oo] = vi;
+  }
+}
+
+__global__ void fill_kernel(double* p, int64_t n, double v) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += stride) p[t] = v;
+}
+
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+
+struct UpdArgs {
+  int64_t no, nv, n1, n2, total;
+  double* xr; double* xi;
+  const double* rr; const double* ri;
+  double* hr_; double* hi_;
+  double h;
+  int mode, start;
+  const double* mo[2]; const double* mv[2]; const double* fo[2]; const double* fv[2];
+  unsigned long long* delta;
+};
+
+__global__ __launch_bounds__(256) void update_kernel(UpdArgs u) {
+  __shared__ double red[4];
+  double dmax = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < u.total; k += stride) {
+    double mask, dd;
+    if (k < 2 * u.n1) {
+      const int s = k >= u.n1;
+      const int64_t r = k - s * u.n1, i = r / u.nv, a = r - i * u.nv;
+      mask = u.mo[s][i] * u.mv[s][a];
+      dd = u.fo[s][i] - u.fv[s][a];
+    } else {
+      const int64_t k2 = k - 2 * u.n1;
+      const int blk = (int)(k2 / u.n2);
+      const int s1 = blk == 2, s2 = blk != 0;
+      int64_t r = k2 - blk * u.n2;
+      const int64_t b = r % u.nv; r /= u.nv;
+      const int64_t a = r % u.nv; r /= u.nv;
+      const int64_t j = r % u.no, i = r / u.no;
+      mask = u.mo[s1][i] * u.mo[s2][j] * u.mv[s1][a] * u.mv[s2][b];
+      dd = u.fo[s1][i] + u.fo[s2][j] - u.fv[s1][a] - u.fv[s2][b];
+    }
+    const double xr = u.xr[k], xi = u.xi[k], rr = u.rr[k], ri = u.ri[k];
+    double hr, hi;
+    if (u.start) {
+      hr = xr - u.h * ri;
+      hi = xi + u.h * rr;
+      u.hr_[k] = hr;
+      u.hi_[k] = hi;
+    } else {
+      hr = u.hr_[k];
+      hi = u.hi_[k];
+    }
+    double nr, ni;
+    if (u.mode == 0) {
+      nr = hr - u.h * ri;
+      ni = hi + u.h * rr;
+    } else {
+      const double pr = rr + dd * xr, pi = ri + dd * xi;
+      const double numr = hr - u.h * pi, numi = hi + u.h * pr;
+      const double di = u.h * dd, den = 1.0 + di * di;
+      nr = (numr + numi * di) / den;
+      ni = (numi - numr * di) / den;
+    }
+    if (mask == 0.0) { nr = 0.0; ni = 0.0; }
+    const double dr = nr - xr, dq = ni - xi;
+    const double dv = sqrt(dr * dr + dq * dq);
+    dmax = (dv != dv) ? dv : fmax(dmax, dv);   // keep NaN
+    u.xr[k] = nr;
+    u.xi[k] = ni;
+  }
+  // NaN-propagating max over the block; doubles >= 0 order like their bit patterns
+  unsigned long long bits = __double_as_longlong(dmax);
+  for (int o = 32; o > 0; o >>= 1) {
+    unsigned long long other = __shfl_xor(bits, o);
+    bits = other > bits ? other : bits;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = __longlong_as_double(bits);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long m = 0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) {
+      unsigned long long v = __double_as_longlong(red[w]);
+      m = v > m ? v : m;
+    }
+    atomicMax(u.delta, m);
+  }
+}
+
+struct EnArgs {
+  int64_t no, nv, n1, n2;
+  const double* xr; const double* xi;
+  const double* jov;
+  const double* fov0; const double* fov1; int64_t ld;
+  int ft1;
+  double* part;
+  double* out;
+};
+
+constexpr int kEnergyBlocks = 1024;
+
+__global__ __launch_bounds__(256) void energy_pass1(EnArgs e) {
+  __shared__ double sr[4], si[4];
+  const int64_t total = e.no * e.nv * e.no * e.nv;
+  const double* T1r = e.xr;
+  const double* T1i = e.xi;
+  const double* Tr = e.xr + 2 * e.n1;
+  const double* Ti = e.xi + 2 * e.n1;
+  double accr = 0.0, acci = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    int64_t r = t;
+    const int64_t b = r % e.nv; r /= e.nv;
+    const int64_t j = r % e.no; r /= e.no;
+    const int64_t a = r % e.nv; const int64_t i = r / e.nv;
+    const double J = e.jov[t];
+    const int64_t p = ((i * e.no + j) * e.nv + a) * e.nv + b;
+    double wr = 0.5 * (Tr[p] + Tr[2 * e.n2 + p]) + Tr[e.n2 + p];
+    double wi = 0.5 * (Ti[p] + Ti[2 * e.n2 + p]) + Ti[e.n2 + p];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      const int64_t o = s * e.n1;
+      double xr1 = T1r[o + i * e.nv + a], xi1 = T1i[o + i * e.nv + a];
+      double yr1 = T1r[o + j * e.nv + b], yi1 = T1i[o + j * e.nv + b];
+      wr += 0.5 * (xr1 * yr1 - xi1 * yi1);
+      wi += 0.5 * (xr1 * yi1 + xi1 * yr1);
+      xr1 = T1r[o + i * e.nv + b]; xi1 = T1i[o + i * e.nv + b];
+      yr1 = T1r[o + j * e.nv + a]; yi1 = T1i[o + j * e.nv + a];
+      wr -= 0.5 * (xr1 * yr1 - xi1 * yi1);
+      wi -= 0.5 * (xr1 * yi1 + xi1 * yr1);
+    }
+    {
+      const double xr1 = T1r[i * e.nv + a], xi1 = T1i[i * e.nv + a];
+      const double yr1 = T1r[e.n1 + j * e.nv + b], yi1 = T1i[e.n1 + j * e.nv + b];
+      wr += xr1 * yr1 - xi1 * yi1;
+      wi += xr1 * yi1 + xi1 * yr1;
+    }
+    accr += J * wr;
+    acci += J * wi;
+  }
+  accr = wave_sum(accr);
+  acci = wave_sum(acci);
+  if ((threadIdx.x & 63) == 0) { sr[threadIdx.x >> 6] = accr; si[threadIdx.x >> 6] = acci; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, c = 0.0;
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) { a += sr[w]; c += si[w]; }
+    e.part[2 * blockIdx.x] = a;
+    e.part[2 * blockIdx.x + 1] = c;
+  }
+}
+
+__global__ __launch_bounds__(64) void energy_pass2(EnArgs e, int nparts) {
+  // one wave: fixed-order sums, then the f_ia t_ia term
+  double ar = 0.0, ai = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 64) { ar += e.part[2 * k]; ai += e.part[2 * k + 1]; }
+  if (e.ft1) {
+    for (int64_t k = threadIdx.x; k < 2 * e.n1; k += 64) {
+      const int s = k >= e.n1;
+      const int64_t r = k - s * e.n1, i = r / e.nv, a = r - i * e.nv;
+      const double f = (s ? e.fov1 : e.fov0)[i * e.ld + a];
+      ar += f * e.xr[k];
+      ai += f * e.xi[k];
+    }
+  }
+  ar = wave_sum(ar);
+  ai = wave_sum(ai);
+  if (threadIdx.x == 0) { e.out[0] = ar; e.out[1] = ai; }
+}
+
+__global__ void cumulant_kernel(double* c, int64_t k, const double* ep, const double* en, double h) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const double sr = ep[0] + en[0], si = ep[1] + en[1];
+    c[2 * (k + 1)] = c[2 * k] - h * si;
+    c[2 * (k + 1) + 1] = c[2 * k + 1] + h * sr;
+  }
+}
+
+int grid_for(int64_t n, int per_block = 256) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
+}
+
+class HipBackend : public Backend {
+ public:
+  explicit HipBackend(hipStream_t s) : stream_(s) {}
+  ~HipBackend() override {}
+
+  void* alloc(size_t bytes) override {
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      return nullptr;
+    }
+    return p;
+  }
+  void release(void* p) override { record(hipFree(p), "hipFree"); }
+  void h2d(void* d, const void* s, size_t b) override {
+    record(hipMemcpyAsync(d, s, b, hipMemcpyHostToDevice, stream_), "hipMemcpyAsync H2D");
+    record(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+  }
+  void d2h(void* d, const void* s, size_t b) override {
+    record(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToHost, stream_), "hipMemcpyAsync D2H");
+    record(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+  }
+  void d2d(void* d, const void* s, size_t b) override {
+    record(hipMemcpyAsync(d, s, b, hipMemcpyDeviceToDevice, stream_), "hipMemcpyAsync D2D");
+  }
+  void fill(double* p, int64_t n, double v) override {
+    if (n <= 0) return;
+    fill_kernel<<<grid_for(n), 256, 0, stream_>>>(p, n, v);
+    launched("fill");
+  }
+  void sync() override { record(hipStreamSynchronize(stream_), "hipStreamSynchronize"); }
+  bool ok(std::string* msg) override {
+    if (!err_.empty()) {
+      *msg = err_;
+      return false;
+    }
+    return true;
+  }
+  int64_t energy_partials() const override { return 2 * kEnergyBlocks; }
+
+  void gemm(const GemmOp& op) override {
+    if (op.prec != 0) {
+      set_err("only float64 contractions are built into this library");
+      return;
+    }
+    GemmArgs g;
+    g.M = op.M; g.N = op.N; g.K = op.K; g.batch = op.batch;
+    g.ar = op.a_re; g.ai = op.a_im; g.asm_ = op.a_sm; g.ask = op.a_sk; g.asb = op.a_sb;
+    g.br = op.b_re; g.bi = op.b_im; g.bsk = op.b_sk; g.bsn = op.b_sn; g.bsb = op.b_sb;
+    g.cr = op.c_re; g.ci = op.c_im; g.csm = op.c_sm; g.csn = op.c_sn; g.csb = op.c_sb;
+    g.alpha = op.alpha;
+    g.beta = op.beta;
+    g.tiles_m = (op.M + BM - 1) / BM;
+    g.tiles_n = (op.N + BN - 1) / BN;
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    if (tiles > 0x7fffffffLL) {
+      set_err("gemm: too many tiles");
+      return;
+    }
+    dim3 grid((unsigned)tiles, (unsigned)std::min<int64_t>(op.batch, 65535));
+    const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
+    const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
+#define RTEOM_GEMM(AC, BC)                                                                     \
+  do {                                                                                       \
+    if (akc && bkc) gemm_f64<AC, BC, true, true><<<grid, kThreads, 0, stream_>>>(g);          \
+    else if (akc) gemm_f64<AC, BC, true, false><<<grid, kThreads, 0, stream_>>>(g);           \
+    else if (bkc) gemm_f64<AC, BC, false, true><<<grid, kThreads, 0, stream_>>>(g);           \
+    else gemm_f64<AC, BC, false, false><<<grid, kThreads, 0, stream_>>>(g);                   \
+  } while (0)
+    if (ac && bc) RTEOM_GEMM(true, true);
+    else if (ac) RTEOM_GEMM(true, false);
+    else if (bc) RTEOM_GEMM(false, true);
+    else RTEOM_GEMM(false, false);
+#undef RTEOM_GEMM
+    launched("gemm_f64");
+  }
+
+  void permute(const PermOp& op) override {
+    PermArgs p;
+    p.nd = op.nd;
+    p.total = 1;
+    for (int d = 0; d < kMaxDims; ++d) {
+      p.dim[d] = d < op.nd ? op.dim[d] : 1;
+      p.istr[d] = d < op.nd ? op.in_str[d] : 0;
+      p.ostr[d] = d < op.nd ? op.out_str[d] : 0;
+      p.sc[d] = d < op.nd ? op.scale[d] : nullptr;
+      if (d < op.nd) p.total *= op.dim[d];
+    }
+    if (p.total == 0) return;
+    p.ir = op.in_re; p.ii = op.in_im; p.orr = op.out_re; p.oi = op.out_im;
+    p.ar = op.alpha_re; p.ai = op.alpha_im; p.beta = op.beta;
+    permute_kernel<<<grid_for(p.total), 256, 0, stream_>>>(p);
+    launched("permute");
+  }
+
+  void update(const UpdateOp& u) override {
+    UpdArgs a;
+    a.no = u.lay.no; a.nv = u.lay.nv; a.n1 = u.lay.n1(); a.n2 = u.lay.n2(); a.total = u.lay.size();
+    a.xr = u.x_re; a.xi = u.x_im; a.rr = u.r_re; a.ri = u.r_im; a.hr_ = u.rhs_re; a.hi_ = u.rhs_im;
+    a.h = u.h; a.mode = u.mode; a.start = u.start;
+    for (int s = 0; s < 2; ++s) {
+      a.mo[s] = u.sv.mo[s]; a.mv[s] = u.sv.mv[s]; a.fo[s] = u.sv.fo[s]; a.fv[s] = u.sv.fv[s];
+    }
+    a.delta = reinterpret_cast<unsigned long long*>(u.delta);
+    update_kernel<<<grid_for(a.total), 256, 0, stream_>>>(a);
+    launched("update");
+  }
+
+  void energy(const EnergyOp& op) override {
+    EnArgs e;
+    e.no = op.lay.no; e.nv = op.lay.nv; e.n1 = op.lay.n1(); e.n2 = op.lay.n2();
+    e.xr = op.x_re; e.xi = op.x_im; e.jov = op.jov;
+    e.fov0 = op.fov[0]; e.fov1 = op.fov[1]; e.ld = op.fov_ld; e.ft1 = op.include_ft1;
+    e.part = op.partial; e.out = op.e_out;
+    energy_pass1<<<kEnergyBlocks, 256, 0, stream_>>>(e);
+    launched("energy_pass1");
+    energy_pass2<<<1, 64, 0, stream_>>>(e, kEnergyBlocks);
+    launched("energy_pass2");
+  }
+
+  void cumulant_append(double* c, int64_t k, const double* ep, const double* en, double h) override {
+    cumulant_kernel<<<1, 64, 0, stream_>>>(c, k, ep, en, h);
+    launched("cumulant");
+  }
+
+ private:
+  hipStream_t stream_;
+  std::string err_;
+  void set_err(const std::string& m) {
+    if (err_.empty()) err_ = m;
+  }
+  void record(hipError_t e, const char* what) {
+    if (e != hipSuccess) set_err(std::string(what) + ": " + hipGetErrorString(e));
+  }
+  void launched(const char* what) { record(hipGetLastError(), what); }
+};
+
+}  // namespace
+
+Backend* make_hip_backend(void* stream, std::string* err) {
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n == 0) {
+    (void)hipGetLastError();
+    if (err) *err = "no HIP device";
+    return nullptr;
+  }
+  return new HipBackend(static_cast<hipStream_t>(stream));
+}
+
+}  // namespace rteom

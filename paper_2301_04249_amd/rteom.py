@@ -1,0 +1,219 @@
+"""ctypes binding of the C ABI declared in include/rteom.h.
+
+Argument marshalling only: every step of the hot path runs in the HIP library
+``librteom.so`` built in this directory.  PyTorch is used for the device
+workspace and the stream; importing this module never falls back to any other
+implementation -- if the library is missing it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librteom.so")
+
+STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NONFINITE",
+          6: "ERR_STATE"}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+
+# every exported symbol of include/rteom.h
+SYMBOLS = (
+    "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
+    "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_residual_flops", "rteom_free", "rteom_last_error",
+)
+
+
+class RteomError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("prec", ctypes.c_int32),
+        ("fp_map", ctypes.c_int32),
+        ("fp_fixed_iters", ctypes.c_int32),
+        ("fp_max_iter", ctypes.c_int32),
+        ("fp_tol", ctypes.c_double),
+        ("dC_include_fT1", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("max_steps", ctypes.c_int64),
+        ("stream", ctypes.c_void_p),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_size_t),
+    ]
+
+
+_LIBS = {}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+
+
+def load(path: str = LIB_PATH):
+    """Load (once) the library at ``path`` and declare the ABI signatures."""
+    if path in _LIBS:
+        return _LIBS[path]
+    if not os.path.exists(path):
+        raise RuntimeError(f"RT-EOM-CCSD library not built: {path} is missing (run __graft_entry__.build())")
+    lib = ctypes.CDLL(path)
+    c = ctypes
+    lib.rteom_default_options.argtypes = [c.POINTER(Options)]
+    lib.rteom_default_options.restype = None
+    lib.rteom_workspace_query.argtypes = [c.c_int32] * 6 + [c.POINTER(Options), c.POINTER(c.c_size_t)]
+    lib.rteom_init.argtypes = [c.POINTER(c.c_void_p), c.c_int32, c.c_int32, c.c_int32, _dp, c.c_int32, _dp,
+                               c.c_int32, c.c_int32, c.POINTER(Options)]
+    lib.rteom_step.argtypes = [c.c_void_p, c.c_double, c.c_int32, _ip]
+    lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
+    lib.rteom_dims.argtypes = [c.c_void_p, _ip, _ip, _ip, _ip]
+    lib.rteom_set_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
+    lib.rteom_get_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
+    lib.rteom_residual.argtypes = [c.c_void_p, _dp, _dp]
+    lib.rteom_energy.argtypes = [c.c_void_p, _dp]
+    lib.rteom_residual_flops.argtypes = [c.c_void_p, _dp]
+    lib.rteom_free.argtypes = [c.c_void_p]
+    lib.rteom_last_error.argtypes = [c.c_void_p]
+    lib.rteom_last_error.restype = c.c_char_p
+    for name in SYMBOLS:
+        if name not in ("rteom_default_options", "rteom_last_error"):
+            getattr(lib, name).restype = c.c_int
+    _LIBS[path] = lib
+    return lib
+
+
+def _ptr(a):
+    return a.ctypes.data_as(_dp) if a is not None else None
+
+
+class Propagator:
+    """One core-hole propagation (rteom_init ... rteom_free)."""
+
+    def __init__(self, eps, chol, n_occ_a, n_occ_b, core_orb=0, core_spin=1, prec="fp64", fp_map=0,
+                 fixed_iters=0, max_iter=50, tol=1e-10, include_ft1=True, max_steps=100000,
+                 stream=None, workspace=None, lib_path=LIB_PATH):
+        self.lib = load(lib_path)
+        eps = np.ascontiguousarray(eps, dtype=np.float64)
+        chol = np.ascontiguousarray(chol, dtype=np.float64)
+        nq, n, n2 = chol.shape
+        assert n == n2 == eps.shape[0]
+        opt = Options()
+        self.lib.rteom_default_options(ctypes.byref(opt))
+        opt.prec = PREC[prec] if isinstance(prec, str) else int(prec)
+        opt.fp_map = int(fp_map)
+        opt.fp_fixed_iters = int(fixed_iters)
+        opt.fp_max_iter = int(max_iter)
+        opt.fp_tol = float(tol)
+        opt.dC_include_fT1 = 1 if include_ft1 else 0
+        opt.max_steps = int(max_steps)
+        opt.stream = stream
+        self._ws = None
+        if workspace == "torch":
+            import torch
+            need = ctypes.c_size_t(0)
+            st = self.lib.rteom_workspace_query(n, n_occ_a, n_occ_b, nq, core_orb, core_spin, ctypes.byref(opt),
+                                                ctypes.byref(need))
+            self._check(st, None)
+            self._ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+            opt.workspace = self._ws.data_ptr()
+            opt.workspace_bytes = int(need.value)
+            if stream is None:
+                opt.stream = torch.cuda.current_stream().cuda_stream
+        self.opt = opt
+        h = ctypes.c_void_p()
+        st = self.lib.rteom_init(ctypes.byref(h), n, n_occ_a, n_occ_b, _ptr(eps), nq, _ptr(chol), core_orb,
+                                 core_spin, ctypes.byref(opt))
+        self._check(st, None)
+        self.h = h
+        no, nv = ctypes.c_int32(), ctypes.c_int32()
+        self.lib.rteom_dims(self.h, ctypes.byref(no), ctypes.byref(nv), None, None)
+        self.no, self.nv = no.value, nv.value
+        occ = np.zeros(self.no, dtype=np.int32)
+        vir = np.zeros(self.nv, dtype=np.int32)
+        self.lib.rteom_dims(self.h, None, None, occ.ctypes.data_as(_ip), vir.ctypes.data_as(_ip))
+        self.occ_list, self.vir_list = occ, vir
+
+    def _check(self, st, h):
+        if st != 0:
+            msg = self.lib.rteom_last_error(h)
+            raise RteomError(st, msg.decode() if msg else "")
+
+    # -- amplitude layout helpers (host)
+    def t1_shape(self):
+        return (2, self.no, self.nv)
+
+    def t2_shape(self):
+        return (3, self.no, self.no, self.nv, self.nv)
+
+    def step(self, dt, n_steps=1):
+        iters = np.zeros(max(n_steps, 1), dtype=np.int32)
+        st = self.lib.rteom_step(self.h, float(dt), int(n_steps), iters.ctypes.data_as(_ip))
+        self._check(st, self.h)
+        return iters[:n_steps]
+
+    def cumulant(self):
+        """(times, C) for t_0 = 0 ... t_n (rteom_cumulant)."""
+        n = ctypes.c_int64()
+        st = self.lib.rteom_cumulant(self.h, 0, None, None, ctypes.byref(n))   # query the length
+        self._check(st, self.h)
+        total = n.value
+        t = np.zeros(max(total, 1))
+        c = np.zeros((max(total, 1), 2))
+        st = self.lib.rteom_cumulant(self.h, total, _ptr(t), _ptr(c), ctypes.byref(n))
+        self._check(st, self.h)
+        return t[: n.value], c[: n.value, 0] + 1j * c[: n.value, 1]
+
+    def set_amplitudes(self, t1, t2):
+        t1 = np.ascontiguousarray(t1, dtype=np.complex128).reshape(self.t1_shape())
+        t2 = np.ascontiguousarray(t2, dtype=np.complex128).reshape(self.t2_shape())
+        st = self.lib.rteom_set_amplitudes(self.h, t1.view(np.float64).ctypes.data_as(_dp),
+                                           t2.view(np.float64).ctypes.data_as(_dp))
+        self._check(st, self.h)
+
+    def get_amplitudes(self):
+        t1 = np.zeros(self.t1_shape(), dtype=np.complex128)
+        t2 = np.zeros(self.t2_shape(), dtype=np.complex128)
+        st = self.lib.rteom_get_amplitudes(self.h, t1.view(np.float64).ctypes.data_as(_dp),
+                                           t2.view(np.float64).ctypes.data_as(_dp))
+        self._check(st, self.h)
+        return t1, t2
+
+    def residual(self, want=True):
+        if not want:
+            st = self.lib.rteom_residual(self.h, None, None)
+            self._check(st, self.h)
+            return None
+        r1 = np.zeros(self.t1_shape(), dtype=np.complex128)
+        r2 = np.zeros(self.t2_shape(), dtype=np.complex128)
+        st = self.lib.rteom_residual(self.h, r1.view(np.float64).ctypes.data_as(_dp),
+                                     r2.view(np.float64).ctypes.data_as(_dp))
+        self._check(st, self.h)
+        return r1, r2
+
+    def energy(self):
+        e = np.zeros(2)
+        st = self.lib.rteom_energy(self.h, _ptr(e))
+        self._check(st, self.h)
+        return complex(e[0], e[1])
+
+    def residual_flops(self):
+        f = ctypes.c_double()
+        st = self.lib.rteom_residual_flops(self.h, ctypes.byref(f))
+        self._check(st, self.h)
+        return f.value
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rteom_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

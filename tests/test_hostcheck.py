@@ -1,0 +1,82 @@
+"""Host logic of the engine (contraction planner, spin-blocked residual sequence,
+step bookkeeping) checked on the CPU against the oracle.
+
+The engine is compiled here over a host implementation of its device operations
+(tests/_hostcheck/librteom_hostcheck.so, built by paper_2301_04249_amd.build);
+the GPU tests run the same engine over the HIP kernels.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import blocks
+from oracle import ccsd, propagate, reference
+from paper_2301_04249_amd import rteom
+from synthetic import Shape, draw_system
+
+LIB = os.path.join(os.path.dirname(__file__), "_hostcheck", "librteom_hostcheck.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="host-check library not built")
+
+
+@pytest.mark.parametrize("case", [
+    (3, 4, 3, 3, 0, 1), (3, 4, 3, 3, 0, 0), (3, 4, 3, 2, 1, 0), (4, 5, 4, 4, 1, 1), (2, 3, 2, 1, 0, 0),
+])
+def test_residual_and_energy_vs_oracle(case):
+    o, v, na, nb, co, cs = case
+    eps, chol = draw_system(Shape(o, v, 10), cfg=99, chol_scale=3.0)
+    sysm = reference.n_minus_one_reference(eps, chol, na, nb, co, cs)
+    P = rteom.Propagator(eps, chol, na, nb, co, cs, lib_path=LIB)
+    t1, t2 = blocks.random_spin_orbital_amplitudes(sysm, 5)
+    b1, b2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, t1, t2)
+    P.set_amplitudes(b1, b2)
+    r1, r2 = P.residual()
+    e1, e2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, *ccsd.residual(sysm, t1, t2))
+    scale = max(np.abs(e2).max(), 1.0)
+    assert np.abs(r1 - e1).max() < 1e-12 * scale
+    assert np.abs(r2 - e2).max() < 1e-12 * scale
+    assert abs(P.energy() - ccsd.energy(sysm, t1, t2)) < 1e-12
+
+
+@pytest.mark.parametrize("kw", [dict(fixed_iters=3), dict(tol=1e-12), dict(tol=1e-12, fp_map=1)])
+def test_propagation_vs_oracle(kw):
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    sysm = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, **kw)
+    it = P.step(0.025, 10)
+    t, c = P.cumulant()
+    tr = propagate.propagate(sysm, 0.025, 10, fixed_iters=kw.get("fixed_iters"), tol=kw.get("tol", 1e-13),
+                             fp_map="denominator" if kw.get("fp_map") else "plain")
+    assert np.array_equal(it, tr.iters)
+    assert np.abs(c - tr.cumulant).max() < 1e-14
+    assert np.allclose(t, tr.times)
+
+
+def test_noconvergence_reported():
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, tol=1e-14, max_iter=2)
+    with pytest.raises(rteom.RteomError) as ex:
+        P.step(0.05, 1)
+    assert ex.value.status == 4
+    with pytest.raises(rteom.RteomError) as ex:
+        P.step(0.05, 1)
+    assert ex.value.status == 6   # failed state until amplitudes are reset
+
+
+def test_input_validation():
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    bad = chol.copy()
+    bad[0, 0, 1] += 1e-3
+    with pytest.raises(rteom.RteomError) as ex:
+        rteom.Propagator(eps, bad, 3, 3, 0, 1, lib_path=LIB)
+    assert ex.value.status == 1
+    nan = eps.copy()
+    nan[2] = np.nan
+    with pytest.raises(rteom.RteomError) as ex:
+        rteom.Propagator(nan, chol, 3, 3, 0, 1, lib_path=LIB)
+    assert ex.value.status == 5
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB)
+    with pytest.raises(rteom.RteomError) as ex:
+        P.step(-0.1, 1)
+    assert ex.value.status == 1

@@ -136,6 +136,18 @@ rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
    them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex). */
 rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
 
+/* Device timing by phase of the hot path: 0 particle-ladder GEMM, 1 o^3 v^3 ring / W / Z
+   GEMMs, 2 other GEMMs, 3 tensor moves, 4 trapezoid update, 5 energy and C(t).  HIP events
+   are recorded around every operation of the phases whose bit is set in phase_mask, on the
+   context's stream; 0 switches timing off.  For benchmarking and profiling. */
+rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask);
+
+/* Statistics of one phase since the previous query of that phase: *ms device time of its
+   operations (0 unless profiled), *ops operations timed, *flops the phase's flops in one
+   residual evaluation (same convention as rteom_residual_flops).  Synchronises the stream. */
+rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops,
+                               int64_t* ops);
+
 /* Release the context (NULL-safe). */
 rteom_status rteom_free(rteom_ctx* ctx);
 

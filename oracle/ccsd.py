@@ -6,7 +6,7 @@ below is the textbook spin-orbital CCSD projection for a general
 (non-canonical) Fock operator, in the intermediate form of Stanton, Gauss,
 Watts and Bartlett (J. Chem. Phys. 94, 4334 (1991)).  It is pinned against a
 brute-force determinant-space evaluation of the definition
-(tests/test_oracle_fockspace.py).
+(tests/test_oracle_pins.py).
 
 The residual returned is R = RHS - D*t (D_ia = f_ii - f_aa,
 D_ijab = f_ii + f_jj - f_aa - f_bb), i.e. exactly <Phi_x|e^{-T} H_N e^{T}|Phi>.
@@ -21,12 +21,12 @@ from __future__ import annotations
 
 import numpy as np
 
-from .reference import SpinOrbitalSystem
+from .reference import SpinOrbitalSystem, particle_ladder
 
 
 def _blocks(sys: SpinOrbitalSystem):
     b = {}
-    for spec in ("oooo", "ooov", "oovv", "ovov", "ovvo", "ovvv", "vvvv", "vovv", "oovo",
+    for spec in ("oooo", "ooov", "oovv", "ovov", "ovvo", "ovvv", "vovv", "oovo",
                  "vvvo", "ovoo"):
         b[spec] = sys.block(spec)
     for spec in ("oo", "ov", "vv"):
@@ -48,7 +48,7 @@ def residual(sys: SpinOrbitalSystem, t1: np.ndarray, t2: np.ndarray, blocks=None
     b = blocks if blocks is not None else _blocks(sys)
     foo, fov, fvv = b["foo"], b["fov"], b["fvv"]
     oooo, ooov, oovv = b["oooo"], b["ooov"], b["oovv"]
-    ovvo, ovvv, vvvv = b["ovvo"], b["ovvv"], b["vvvv"]
+    ovvo, ovvv = b["ovvo"], b["ovvv"]
     vovv, oovo, vvvo, ovoo = b["vovv"], b["oovo"], b["vvvo"], b["ovoo"]
     ein = lambda s, *a: np.einsum(s, *a, optimize=True)  # noqa: E731
 
@@ -77,9 +77,9 @@ def residual(sys: SpinOrbitalSystem, t1: np.ndarray, t2: np.ndarray, blocks=None
     wmnij = (oooo
              + _perm_ij_last(ein("je,mnie->mnij", t1, ooov))
              + 0.25 * ein("ijef,mnef->mnij", tau, oovv))
-    wabef = (vvvv
-             - _perm_ab_first(ein("mb,amef->abef", t1, vovv))
-             + 0.25 * ein("mnab,mnef->abef", tau, oovv))
+    # W_abef = <ab||ef> - P(ab) t_m^b <am||ef> + 1/4 tau_mn^ab <mn||ef> enters only
+    # through 1/2 sum_ef tau_ij^ef W_abef, evaluated below term by term so that
+    # no (virtual)^4 intermediate is formed.
     wmbej = (ovvo
              + ein("jf,mbef->mbej", t1, ovvv)
              - ein("nb,mnej->mbej", t1, oovo)
@@ -103,7 +103,9 @@ def residual(sys: SpinOrbitalSystem, t1: np.ndarray, t2: np.ndarray, blocks=None
     r2 = r2 + _perm_ab(ein("ijae,be->ijab", t2, fbe_eff))
     r2 = r2 - _perm_ij(ein("imab,mj->ijab", t2, fmj_eff))
     r2 = r2 + 0.5 * ein("mnab,mnij->ijab", tau, wmnij)
-    r2 = r2 + 0.5 * ein("ijef,abef->ijab", tau, wabef)
+    r2 = r2 + particle_ladder(sys, tau)
+    r2 = r2 - _perm_ab(ein("mb,ijam->ijab", t1, 0.5 * ein("ijef,amef->ijam", tau, vovv)))
+    r2 = r2 + 0.125 * ein("mnab,ijmn->ijab", tau, ein("ijef,mnef->ijmn", tau, oovv))
     ring = ein("imae,mbej->ijab", t2, wmbej) - ein("ie,ma,mbej->ijab", t1, t1, ovvo)
     r2 = r2 + _perm_ij(_perm_ab(ring))
     r2 = r2 + _perm_ij(ein("ie,abej->ijab", t1, vvvo))

@@ -25,7 +25,8 @@ class SpinOrbitalSystem:
     vir: np.ndarray           # spin-orbital indices unoccupied in Phi
     core: int                 # spin-orbital index of c
     fock: np.ndarray          # [2n, 2n] f_pq of the (N-1) reference
-    g: np.ndarray             # [2n, 2n, 2n, 2n] <pq||rs>
+    g: object                 # [2n, 2n, 2n, 2n] <pq||rs>, or None (lean: blocks on demand)
+    _cache: dict = dataclasses.field(default_factory=dict)
 
     @property
     def nso(self) -> int:
@@ -42,7 +43,11 @@ class SpinOrbitalSystem:
     def block(self, spec: str) -> np.ndarray:
         """Sub-block of <pq||rs> with 'o'/'v' per index, e.g. 'oovv'."""
         idx = [self.occ if c == "o" else self.vir for c in spec]
-        return self.g[np.ix_(*idx)]
+        if self.g is not None:
+            return self.g[np.ix_(*idx)]
+        if spec not in self._cache:
+            self._cache[spec] = antisymmetrized_block(self.chol, self.n, *idx)
+        return self._cache[spec]
 
     def fblock(self, spec: str) -> np.ndarray:
         idx = [self.occ if c == "o" else self.vir for c in spec]
@@ -70,11 +75,29 @@ def antisymmetrized_spin_orbital(eri: np.ndarray) -> np.ndarray:
     return phys - phys.transpose(0, 1, 3, 2)
 
 
+def antisymmetrized_block(chol, n, P, Q, R, S):
+    """<pq||rs> for spin-orbital index lists P, Q, R, S, built from the Cholesky vectors."""
+    P, Q, R, S = (np.asarray(x) for x in (P, Q, R, S))
+    sp = lambda x: x % n  # noqa: E731
+    ss = lambda x: x // n  # noqa: E731
+    # <pq|rs> = (pr|qs) delta(s_p, s_r) delta(s_q, s_s)
+    pr = np.einsum("kpr,kqs->pqrs", chol[:, sp(P)][:, :, sp(R)], chol[:, sp(Q)][:, :, sp(S)], optimize=True)
+    pr *= (ss(P)[:, None, None, None] == ss(R)[None, None, :, None])
+    pr *= (ss(Q)[None, :, None, None] == ss(S)[None, None, None, :])
+    # <pq|sr> = (ps|qr) delta(s_p, s_s) delta(s_q, s_r)
+    ps = np.einsum("kps,kqr->pqrs", chol[:, sp(P)][:, :, sp(S)], chol[:, sp(Q)][:, :, sp(R)], optimize=True)
+    ps *= (ss(P)[:, None, None, None] == ss(S)[None, None, None, :])
+    ps *= (ss(Q)[None, :, None, None] == ss(R)[None, None, :, None])
+    return pr - ps
+
+
 def n_minus_one_reference(eps, chol, n_occ_a: int, n_occ_b: int, core_orb: int,
-                          core_spin: int) -> SpinOrbitalSystem:
+                          core_spin: int, lean: bool = False) -> SpinOrbitalSystem:
     """Build the (N-1)-electron reference by removing spin-orbital (core_orb, core_spin).
 
     The N-electron determinant occupies spatial orbitals 0..n_occ_s-1 in spin s.
+    ``lean=True`` never forms the full (2n)^4 integral tensor: integral blocks are
+    built from the Cholesky vectors when first asked for.
     """
     eps = np.asarray(eps, dtype=np.float64)
     chol = np.asarray(chol, dtype=np.float64)
@@ -85,11 +108,16 @@ def n_minus_one_reference(eps, chol, n_occ_a: int, n_occ_b: int, core_orb: int,
         raise ValueError("core spin-orbital is not occupied in the N-electron reference")
     occ = np.array(sorted(set(occ_n) - {core}), dtype=np.int64)
     vir = np.array(sorted(set(range(2 * n)) - set(occ.tolist())), dtype=np.int64)
-    eri = coulomb_from_cholesky(chol)
-    g = antisymmetrized_spin_orbital(eri)
     eps_so = np.concatenate([eps, eps])
+    allso = np.arange(2 * n)
+    if lean:
+        g = None
+        gc = antisymmetrized_block(chol, n, allso, [core], allso, [core])[:, 0, :, 0]
+    else:
+        g = antisymmetrized_spin_orbital(coulomb_from_cholesky(chol))
+        gc = g[:, core, :, core]
     # f_pq = eps_p delta_pq - <pc||qc>  (the Fock definition beside the normal-ordered H_N)
-    fock = np.diag(eps_so) - g[:, core, :, core]
+    fock = np.diag(eps_so) - gc
     return SpinOrbitalSystem(n=n, eps=eps, chol=chol, occ=occ, vir=vir, core=core,
                              fock=fock, g=g)
 
@@ -97,3 +125,33 @@ def n_minus_one_reference(eps, chol, n_occ_a: int, n_occ_b: int, core_orb: int,
 def one_body_core(sys: SpinOrbitalSystem) -> np.ndarray:
     """h_pq implied by the Fock matrix of Phi: h = f - sum_{k in occ(Phi)} <pk||qk>."""
     return sys.fock - np.einsum("pkqk->pq", sys.g[:, sys.occ][:, :, :, sys.occ])
+
+
+def particle_ladder(sys: SpinOrbitalSystem, tau: np.ndarray) -> np.ndarray:
+    """1/2 sum_ef <ab||ef> tau_ijef for a tau antisymmetric in (e, f).
+
+    With the full integral tensor this is the plain contraction.  In lean mode the
+    antisymmetry of tau turns it into sum_ef (ae|bf) tau_ijef with (ae|bf) the
+    spin-orbital Coulomb integral, which connects a with e and b with f of equal
+    spin: it is evaluated for each spin of a and of b with the spatial (ae|bf).
+    """
+    if sys.g is not None:
+        return 0.5 * np.einsum("ijef,abef->ijab", tau, sys.block("vvvv"), optimize=True)
+    n = sys.n
+    vir = sys.vir
+    spat = np.unique(vir % n)
+    pos = {int(p): k for k, p in enumerate(spat)}
+    lv = sys.chol[:, spat][:, :, spat]
+    vsp = np.einsum("kae,kbf->aebf", lv, lv, optimize=True)   # spatial (ae|bf)
+    out = np.zeros(tau.shape[:2] + (len(vir), len(vir)), dtype=complex)
+    for sa in (0, 1):
+        A = np.nonzero(vir // n == sa)[0]
+        ia = [pos[int(vir[k] % n)] for k in A]
+        for sb in (0, 1):
+            B = np.nonzero(vir // n == sb)[0]
+            ib = [pos[int(vir[k] % n)] for k in B]
+            v = vsp[np.ix_(ia, ia, ib, ib)]          # (a e | b f), a,e in spin sa; b,f in spin sb
+            out[np.ix_(np.arange(tau.shape[0]), np.arange(tau.shape[1]), A, B)] = np.einsum(
+                "ijef,aebf->ijab", tau[np.ix_(np.arange(tau.shape[0]), np.arange(tau.shape[1]), A, B)], v,
+                optimize=True)
+    return out

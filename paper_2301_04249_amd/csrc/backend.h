@@ -87,9 +87,28 @@ struct EnergyOp {
   double* partial = nullptr;          // scratch, >= energy_partials() doubles
 };
 
+// Phases of one residual evaluation / time step; device timing can be switched
+// on per phase (HIP events around each operation of a selected phase only).
+enum Phase {
+  kPhaseLadder = 0,   // particle-particle ladder GEMM
+  kPhaseRing = 1,     // o^3 v^3 ring / W / Z GEMMs
+  kPhaseGemm = 2,     // all other GEMMs
+  kPhaseMove = 3,     // permutes, copies, scaling
+  kPhaseUpdate = 4,   // fused trapezoid update
+  kPhaseEnergy = 5,   // energy reduction and C(t) append
+  kNumPhases = 6
+};
+
 class Backend {
  public:
   virtual ~Backend() {}
+  virtual void set_phase(int ph) { phase_ = ph; }
+  virtual void set_profile(unsigned mask) { (void)mask; }
+  // total milliseconds and operation count of the profiled phase since the last call
+  virtual double phase_ms(int ph, int64_t* ops) { (void)ph; if (ops) *ops = 0; return 0.0; }
+ protected:
+  int phase_ = kPhaseGemm;
+ public:
   virtual void* alloc(size_t bytes) = 0;
   virtual void release(void* p) = 0;
   virtual void h2d(void* dst, const void* src, size_t bytes) = 0;

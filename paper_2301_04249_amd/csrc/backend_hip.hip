@@ -16,6 +16,7 @@
 #include <cstdint>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "backend.h"
 
@@ -384,7 +385,30 @@ int grid_for(int64_t n, int per_block = 256) {
 class HipBackend : public Backend {
  public:
   explicit HipBackend(hipStream_t s) : stream_(s) {}
-  ~HipBackend() override {}
+  ~HipBackend() override {
+    for (auto& e : done_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    for (auto& e : pool_) (void)hipEventDestroy(e);
+  }
+
+  void set_profile(unsigned mask) override { mask_ = mask; }
+  double phase_ms(int ph, int64_t* ops) override {
+    record(hipStreamSynchronize(stream_), "hipStreamSynchronize");
+    double total = 0.0;
+    int64_t n = 0;
+    std::vector<Timed> keep;
+    for (auto& e : done_) {
+      if (e.ph != ph) { keep.push_back(e); continue; }
+      float ms = 0.f;
+      record(hipEventElapsedTime(&ms, e.a, e.b), "hipEventElapsedTime");
+      total += ms;
+      ++n;
+      pool_.push_back(e.a);
+      pool_.push_back(e.b);
+    }
+    done_.swap(keep);
+    if (ops) *ops = n;
+    return total;
+  }
 
   void* alloc(size_t bytes) override {
     void* p = nullptr;
@@ -408,8 +432,10 @@ class HipBackend : public Backend {
   }
   void fill(double* p, int64_t n, double v) override {
     if (n <= 0) return;
+    begin();
     fill_kernel<<<grid_for(n), 256, 0, stream_>>>(p, n, v);
     launched("fill");
+    end();
   }
   void sync() override { record(hipStreamSynchronize(stream_), "hipStreamSynchronize"); }
   bool ok(std::string* msg) override {
@@ -441,6 +467,7 @@ class HipBackend : public Backend {
       return;
     }
     dim3 grid((unsigned)tiles, (unsigned)std::min<int64_t>(op.batch, 65535));
+    begin();
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
 #define RTEOM_GEMM(AC, BC)                                                                     \
@@ -456,6 +483,7 @@ class HipBackend : public Backend {
     else RTEOM_GEMM(false, false);
 #undef RTEOM_GEMM
     launched("gemm_f64");
+    end();
   }
 
   void permute(const PermOp& op) override {
@@ -472,8 +500,10 @@ class HipBackend : public Backend {
     if (p.total == 0) return;
     p.ir = op.in_re; p.ii = op.in_im; p.orr = op.out_re; p.oi = op.out_im;
     p.ar = op.alpha_re; p.ai = op.alpha_im; p.beta = op.beta;
+    begin();
     permute_kernel<<<grid_for(p.total), 256, 0, stream_>>>(p);
     launched("permute");
+    end();
   }
 
   void update(const UpdateOp& u) override {
@@ -485,8 +515,10 @@ class HipBackend : public Backend {
       a.mo[s] = u.sv.mo[s]; a.mv[s] = u.sv.mv[s]; a.fo[s] = u.sv.fo[s]; a.fv[s] = u.sv.fv[s];
     }
     a.delta = reinterpret_cast<unsigned long long*>(u.delta);
+    begin();
     update_kernel<<<grid_for(a.total), 256, 0, stream_>>>(a);
     launched("update");
+    end();
   }
 
   void energy(const EnergyOp& op) override {
@@ -495,20 +527,50 @@ class HipBackend : public Backend {
     e.xr = op.x_re; e.xi = op.x_im; e.jov = op.jov;
     e.fov0 = op.fov[0]; e.fov1 = op.fov[1]; e.ld = op.fov_ld; e.ft1 = op.include_ft1;
     e.part = op.partial; e.out = op.e_out;
+    begin();
     energy_pass1<<<kEnergyBlocks, 256, 0, stream_>>>(e);
     launched("energy_pass1");
     energy_pass2<<<1, 64, 0, stream_>>>(e, kEnergyBlocks);
     launched("energy_pass2");
+    end();
   }
 
   void cumulant_append(double* c, int64_t k, const double* ep, const double* en, double h) override {
+    begin();
     cumulant_kernel<<<1, 64, 0, stream_>>>(c, k, ep, en, h);
     launched("cumulant");
+    end();
   }
 
  private:
+  struct Timed { hipEvent_t a, b; int ph; };
   hipStream_t stream_;
   std::string err_;
+  unsigned mask_ = 0;
+  std::vector<Timed> done_;
+  std::vector<hipEvent_t> pool_;
+  hipEvent_t cur_a_ = nullptr;
+  bool timing_ = false;
+  hipEvent_t event() {
+    if (!pool_.empty()) { hipEvent_t e = pool_.back(); pool_.pop_back(); return e; }
+    hipEvent_t e = nullptr;
+    record(hipEventCreate(&e), "hipEventCreate");
+    return e;
+  }
+  void begin() {
+    timing_ = (mask_ >> phase_) & 1u;
+    if (timing_) {
+      cur_a_ = event();
+      record(hipEventRecord(cur_a_, stream_), "hipEventRecord");
+    }
+  }
+  void end() {
+    if (!timing_) return;
+    hipEvent_t b = event();
+    record(hipEventRecord(b, stream_), "hipEventRecord");
+    done_.push_back({cur_a_, b, phase_});
+    timing_ = false;
+  }
   void set_err(const std::string& m) {
     if (err_.empty()) err_ = m;
   }

@@ -152,7 +152,11 @@ void Engine::add(const View& out, const View& in, double alpha_re, double alpha_
   op.alpha_re = alpha_re;
   op.alpha_im = alpha_im;
   op.beta = beta;
-  if (!dry) be->permute(op);
+  if (!dry) {
+    be->set_phase(kPhaseMove);
+    be->permute(op);
+    be->set_phase(phase);
+  }
 }
 
 void Engine::scale(const View& out, const double* const* scale_vecs) {
@@ -315,7 +319,9 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   op.prec = prec;
   (void)group_size;
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
-  flops += 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
+  const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
+  flops += f;
+  phase_flops[phase] += f;
   if (op.M > 0 && op.N > 0 && op.batch > 0 && !dry) {
     if (op.K == 0) {
       // empty sum: C = beta * C

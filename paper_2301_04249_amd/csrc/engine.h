@@ -65,6 +65,12 @@ class Engine {
   Arena* scratch = nullptr;
   int prec = 0;
   double flops = 0.0;       // accumulated GEMM flops (real-flop convention)
+  double phase_flops[kNumPhases] = {0};
+  int phase = kPhaseGemm;
+  void set_phase(int ph) {
+    phase = ph;
+    if (!dry && be) be->set_phase(ph);
+  }
   bool dry = false;          // plan only (workspace query): count scratch, issue nothing
 
   // C[spec_c] = alpha * sum A[spec_a] B[spec_b] + beta * C

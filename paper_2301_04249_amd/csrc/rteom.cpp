@@ -70,6 +70,7 @@ struct Context {
   int64_t nsteps = 0;
   std::vector<double> times;
   double res_flops = 0.0;
+  double res_phase_flops[kNumPhases] = {0};
 
   // ---------------------------------------------------------------- views
   View Lv(double* p, int64_t a, int64_t b) const { return make_view(p, nullptr, {nq, a, b}); }
@@ -271,6 +272,8 @@ struct Context {
     const int64_t Q = nq;
     const size_t mk = arena.mark();
     eng.flops = 0.0;
+    for (double& f : eng.phase_flops) f = 0.0;
+    eng.set_phase(kPhaseGemm);
     View Lov_v = Lv(Lov, no, nv);
     View Ldoo[2], Ldvv[2], Ldvo[2], fd[2], D[2], Lbar[2], Fvv[2], Foo[2];
     // dressed Cholesky vectors L~ = (1 - t) L (1 + t)
@@ -352,6 +355,7 @@ struct Context {
     // and the opposite-spin exchange blocks V(s->u) (m,e in s; j,b in u)
     View Jv = make_view(Jov, nullptr, {no, nv, no, nv});
     View WX[2][2], Vx[2];
+    eng.set_phase(kPhaseRing);
     for (int s = 0; s < 2; ++s)
       for (int u = 0; u < 2; ++u) {
         WX[s][u] = eng.temp({no, nv, nv, no}, true);
@@ -363,14 +367,25 @@ struct Context {
       Vx[s] = eng.temp({no, nv, nv, no}, true);
       eng.contract("jnbf,mfne->mbej", TT(Xs, u, s), Jv, Vx[s], -0.5, 0);
     }
+    eng.set_phase(kPhaseGemm);
     View x = eng.temp({no, no, nv, nv}, true);
     View tau = eng.temp({no, no, nv, nv}, true);
     View g = eng.temp({no, no, no, no}, true);
     View gA = eng.temp({no, no, no, no}, true);
     View Xo = eng.temp({no, no, no, no}, true);
-    View Z = eng.temp({no, no, no, nv}, true);
     View Vl = make_view(Vlad, nullptr, {nv, nv, nv, nv});
     View Bv = make_view(B1, nullptr, {nv, nv, no, nv});
+    // all three doubles blocks are contiguous: [3 * no * no][nv][nv]
+    const int64_t P3 = 3 * (int64_t)no * no;
+    double* x2 = Xs + 2 * lay.n1();
+    double* r2 = Rs + 2 * lay.n1();
+    View T3 = make_view(x2, x2 + lay.size(), {P3, nv, nv});
+    View R3 = make_view(r2, r2 + lay.size(), {P3, nv, nv});
+    // T1 part of the dressed virtual vectors ("Z" terms): Z_ij,mb = sum_ef T_ijef (me|bf)
+    View Z3 = eng.temp({P3, no, nv}, true);
+    eng.set_phase(kPhaseRing);
+    eng.contract("Pef,efmb->Pmb", T3, Bv, Z3, 1.0, 0);
+    eng.set_phase(kPhaseGemm);
     // same-spin doubles
     for (int s = 0; s < 2; ++s) {
       const int u = 1 - s;
@@ -396,22 +411,21 @@ struct Context {
       eng.contract("ib,ja->ijab", t, t, tau, -1.0, 1);
       eng.contract("mnab,mnij->ijab", T, gA, Rv, 0.5, 1);
       eng.contract("mnab,ijmn->ijab", tau, Xo, Rv, 0.5, 1);
-      // particle ladder with the real (ae|bf)
-      eng.contract("ijef,efab->ijab", T, Vl, Rv, 1.0, 1);
-      // T1 part of the dressed virtual vectors ("Z" terms)
-      eng.contract("ijef,efmb->ijmb", T, Bv, Z, 1.0, 0);
-      eng.contract("ma,ijmb->ijab", t, Z, x, -1.0, 0);
+      // Z: -P(ab) sum_m t_ma Z_ij,mb
+      View Zs = make_view(Z3.re + blk * (int64_t)no * no * no * nv, Z3.im + blk * (int64_t)no * no * no * nv,
+                          {no, no, no, nv});
+      eng.contract("ma,ijmb->ijab", t, Zs, x, -1.0, 0);
       eng.add(Rv, x, 1, 0, 1);
       eng.add(Rv, reorder(x, {0, 1, 3, 2}), -1, 0, 1);
       // exchange ring, P(ij) P(ab)
+      eng.set_phase(kPhaseRing);
       eng.contract("imae,mbej->ijab", T, WX[s][s], x, 1.0, 0);
       eng.contract("imae,mbej->ijab", TT(Xs, s, u), Vx[u], x, 1.0, 1);
+      eng.set_phase(kPhaseGemm);
       eng.add(Rv, x, 1, 0, 1);
       eng.add(Rv, reorder(x, {1, 0, 2, 3}), -1, 0, 1);
       eng.add(Rv, reorder(x, {0, 1, 3, 2}), -1, 0, 1);
       eng.add(Rv, reorder(x, {1, 0, 3, 2}), 1, 0, 1);
-      const double* sc[4] = {mo[s], mo[s], mv[s], mv[s]};
-      eng.scale(Rv, sc);
     }
     // alpha-beta doubles
     {
@@ -428,22 +442,36 @@ struct Context {
       eng.contract("ia,jb->ijab", ta, tb, tau, 1.0, 1);
       eng.contract("mnab,mnij->ijab", T, g, Rv, 1.0, 1);
       eng.contract("mnab,ijmn->ijab", tau, Xo, Rv, 1.0, 1);
-      eng.contract("ijef,efab->ijab", T, Vl, Rv, 1.0, 1);
-      eng.contract("ijef,efmb->ijmb", T, Bv, Z, 1.0, 0);
-      eng.contract("ma,ijmb->ijab", ta, Z, Rv, -1.0, 1);
-      View Z2 = make_view(Z.re, Z.im, {no, no, nv, no});
+      View Zs = make_view(Z3.re + (int64_t)no * no * no * nv, Z3.im + (int64_t)no * no * no * nv, {no, no, no, nv});
+      eng.contract("ma,ijmb->ijab", ta, Zs, Rv, -1.0, 1);
+      View Z2 = eng.temp({no, no, nv, no}, true);
+      eng.set_phase(kPhaseRing);
       eng.contract("ijef,fena->ijan", T, Bv, Z2, 1.0, 0);   // sum_ef T_ijef (ae|nf)
+      eng.set_phase(kPhaseGemm);
       eng.contract("nb,ijan->ijab", tb, Z2, Rv, -1.0, 1);
+      eng.set_phase(kPhaseRing);
       eng.contract("imae,mbej->ijab", T, WX[1][1], Rv, 1.0, 1);
       eng.contract("mjae,mbei->ijab", T, WX[0][1], Rv, 1.0, 1);
       eng.contract("imeb,maej->ijab", T, WX[1][0], Rv, 1.0, 1);
       eng.contract("mjeb,maei->ijab", T, WX[0][0], Rv, 1.0, 1);
       eng.contract("imae,mbej->ijab", t2(Xs, 0), Vx[0], Rv, 1.0, 1);
       eng.contract("jmbe,maei->ijab", t2(Xs, 2), Vx[1], Rv, 1.0, 1);
-      const double* sc[4] = {mo[0], mo[1], mv[0], mv[1]};
-      eng.scale(Rv, sc);
+      eng.set_phase(kPhaseGemm);
+    }
+    // particle-particle ladder with the real (ae|bf), all three blocks in one GEMM
+    eng.set_phase(kPhaseLadder);
+    eng.contract("Pef,efab->Pab", T3, Vl, R3, 1.0, 1);
+    eng.set_phase(kPhaseGemm);
+    // zero the amplitudes of spin-orbitals that do not exist
+    {
+      const int sp[3][2] = {{0, 0}, {0, 1}, {1, 1}};
+      for (int b = 0; b < 3; ++b) {
+        const double* sc[4] = {mo[sp[b][0]], mo[sp[b][1]], mv[sp[b][0]], mv[sp[b][1]]};
+        eng.scale(t2(Rs, b), sc);
+      }
     }
     res_flops = eng.flops;
+    for (int k = 0; k < kNumPhases; ++k) res_phase_flops[k] = eng.phase_flops[k];
     arena.release(mk);
   }
 
@@ -492,6 +520,7 @@ struct Context {
     UpdateOp u0 = update_op(true);
     u0.h = 0.5 * dt;
     residual(X, R);
+    be->set_phase(kPhaseUpdate);
     be->fill(delta, 1, 0.0);
     be->update(u0);
     int passes = 1;
@@ -500,6 +529,7 @@ struct Context {
     if (opt.fp_fixed_iters > 0) {
       while (passes < opt.fp_fixed_iters) {
         residual(X, R);
+        be->set_phase(kPhaseUpdate);
         be->fill(delta, 1, 0.0);
         be->update(u);
         ++passes;
@@ -513,12 +543,14 @@ struct Context {
           throw Error(RTEOM_ERR_NOCONV, "fixed point not converged after " + std::to_string(passes) +
                                             " passes (last change " + std::to_string(d) + ")");
         residual(X, R);
+        be->set_phase(kPhaseUpdate);
         be->fill(delta, 1, 0.0);
         be->update(u);
         ++passes;
         be->d2h(&d, delta, sizeof(double));
       }
     }
+    be->set_phase(kPhaseEnergy);
     energy(X, e_hist + 2 * (nsteps + 1));
     be->cumulant_append(c_hist, nsteps, e_hist + 2 * nsteps, e_hist + 2 * (nsteps + 1), 0.5 * dt);
     ++nsteps;
@@ -842,6 +874,25 @@ rteom_status rteom_residual_flops(const rteom_ctx* cctx, double* flops) {
   if (!cctx || !flops) { g_last_error = "bad argument"; return RTEOM_ERR_ARG; }
   *flops = cctx->c.res_flops;
   return RTEOM_OK;
+}
+
+rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask) {
+  if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  ctx->c.be->set_profile(phase_mask);
+  return RTEOM_OK;
+}
+
+rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops, int64_t* ops) {
+  if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  if (phase < 0 || phase >= rteom::kNumPhases) { ctx->c.err = "bad phase"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  return guarded(ctx, [&] {
+    int64_t n = 0;
+    const double t = c.be->phase_ms(phase, &n);
+    if (ms) *ms = t;
+    if (ops) *ops = n;
+    if (flops) *flops = c.res_phase_flops[phase];
+  });
 }
 
 rteom_status rteom_free(rteom_ctx* ctx) {

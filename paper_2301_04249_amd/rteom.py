@@ -23,8 +23,9 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
     "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
-    "rteom_residual_flops", "rteom_free", "rteom_last_error",
+    "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_free", "rteom_last_error",
 )
+PHASES = ("ladder", "ring", "gemm", "move", "update", "energy")
 
 
 class RteomError(RuntimeError):
@@ -77,6 +78,8 @@ def load(path: str = LIB_PATH):
     lib.rteom_residual.argtypes = [c.c_void_p, _dp, _dp]
     lib.rteom_energy.argtypes = [c.c_void_p, _dp]
     lib.rteom_residual_flops.argtypes = [c.c_void_p, _dp]
+    lib.rteom_profile.argtypes = [c.c_void_p, c.c_uint32]
+    lib.rteom_phase_stats.argtypes = [c.c_void_p, c.c_int32, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_free.argtypes = [c.c_void_p]
     lib.rteom_last_error.argtypes = [c.c_void_p]
     lib.rteom_last_error.restype = c.c_char_p
@@ -206,6 +209,22 @@ class Propagator:
         st = self.lib.rteom_residual_flops(self.h, ctypes.byref(f))
         self._check(st, self.h)
         return f.value
+
+    def profile(self, phases=()):
+        """Time the named phases (see PHASES) with HIP events on the library's stream."""
+        mask = 0
+        for ph in phases:
+            mask |= 1 << PHASES.index(ph)
+        st = self.lib.rteom_profile(self.h, mask)
+        self._check(st, self.h)
+
+    def phase_stats(self, phase):
+        """(device ms since the last query, ops timed, flops of this phase per residual)."""
+        ms, fl, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        st = self.lib.rteom_phase_stats(self.h, PHASES.index(phase), ctypes.byref(ms), ctypes.byref(fl),
+                                        ctypes.byref(n))
+        self._check(st, self.h)
+        return ms.value, n.value, fl.value
 
     def close(self):
         if getattr(self, "h", None):

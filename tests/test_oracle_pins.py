@@ -285,3 +285,17 @@ def test_green_function_and_spectrum_free_particle():
     assert abs(peak - (-20.0)) < 1e-4
     lorentz = eta / np.pi / ((omegas + 20.0) ** 2 + eta ** 2)
     assert np.abs(a - lorentz).max() < 2e-2 * lorentz.max()
+
+
+def test_lean_mode_matches_dense():
+    """Lean blocks and the per-spin Coulomb particle ladder equal the dense <pq||rs> path."""
+    eps, chol = draw_system(Shape(3, 6, 14), cfg=5, chol_scale=2.0)
+    dense = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    lean = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1, lean=True)
+    assert lean.g is None
+    assert np.abs(dense.fock - lean.fock).max() < 1e-14
+    t1, t2 = _random_amplitudes(dense, 4)
+    a1, a2 = ccsd.residual(dense, t1, t2)
+    b1, b2 = ccsd.residual(lean, t1, t2)
+    assert np.abs(a1 - b1).max() < 1e-13 and np.abs(a2 - b2).max() < 1e-13
+    assert abs(ccsd.energy(dense, t1, t2) - ccsd.energy(lean, t1, t2)) < 1e-14

@@ -129,7 +129,8 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
       }
       __syncthreads();
     }
-    // ---- epilogue: lane holds C[4*(lane/16) + r][lane % 16] of each 16x16 block
+    // ---- epilogue: for the f64 16x16x4 MFMA, accumulator register r of a lane
+    // holds C[4*r + lane/16][lane % 16] of its 16x16 block
     double* Cr = g.cr + b * g.csb;
     double* Ci = (AC || BC) ? g.ci + b * g.csb : nullptr;
 #pragma unroll
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
       for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * 32 + x * 16 + 4 * (lane >> 4) + r;
+          const int64_t gm = m0 + wm * 32 + x * 16 + 4 * r + (lane >> 4);
           const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * g.csm + gn * g.csn;

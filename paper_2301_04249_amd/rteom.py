@@ -63,6 +63,13 @@ def load(path: str = LIB_PATH):
         return _LIBS[path]
     if not os.path.exists(path):
         raise RuntimeError(f"RT-EOM-CCSD library not built: {path} is missing (run __graft_entry__.build())")
+    # One HIP runtime per process: torch bundles its own libamdhip64.so.7.  Loading
+    # torch first makes the library's libamdhip64.so.7 dependency resolve to that
+    # already-loaded runtime, so device memory and streams are shared with torch.
+    try:
+        import torch  # noqa: F401
+    except ImportError:  # pragma: no cover - host-only use (workspace queries)
+        pass
     lib = ctypes.CDLL(path)
     c = ctypes
     lib.rteom_default_options.argtypes = [c.POINTER(Options)]

@@ -25,6 +25,11 @@ struct GemmOp {
   double alpha = 1.0;
   int beta = 0;      // 0 overwrite, 1 accumulate
   int prec = 0;      // rteom_prec
+  // split-K (batch == 1 only): the K range is cut into `splitk` chunks whose
+  // partial products go to `partial` ([splitk][M][N], planar when complex) and
+  // are summed in a fixed order by a second kernel.
+  int splitk = 1;
+  double* partial = nullptr;
 };
 
 // out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an

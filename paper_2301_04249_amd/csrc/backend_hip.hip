@@ -37,16 +37,21 @@ struct GemmArgs {
   double alpha;
   int beta;
   int64_t tiles_m, tiles_n;
+  int splitk;
+  int64_t kchunk;             // K elements per split (multiple of BK)
+  double* pr; double* pi;     // partials [splitk][M][N]
 };
 
-// A tile [BK][BM] and B tile [BK][BN] in LDS (k-major) so that the MFMA
-// fragment reads (row = lane % 16, k = lane / 16) are unit stride across lanes.
+// Operand tiles are staged k-major in LDS ([BK][BM] for A, [BK][BN] for B) so
+// that the MFMA fragment reads (row = lane % 16, k = lane / 16) are unit stride
+// across lanes.  The next K tile is loaded into registers while the current one
+// is multiplied, into the other of two LDS buffers: one barrier per K tile.
 template <bool AC, bool BC, bool AKC, bool BKC>
 __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
-  __shared__ double sa_r[BK][BM + PAD];
-  __shared__ double sa_i[AC ? BK : 1][BM + PAD];
-  __shared__ double sb_r[BK][BN + PAD];
-  __shared__ double sb_i[BC ? BK : 1][BN + PAD];
+  __shared__ double sa_r[2][BK][BM + PAD];
+  __shared__ double sa_i[AC ? 2 : 1][AC ? BK : 1][BM + PAD];
+  __shared__ double sb_r[2][BK][BN + PAD];
+  __shared__ double sb_i[BC ? 2 : 1][BC ? BK : 1][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -54,62 +59,86 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
   const int64_t tile = blockIdx.x;
   const int64_t tm = tile / g.tiles_n, tn = tile % g.tiles_n;
   const int64_t m0 = tm * BM, n0 = tn * BN;
+  // staging coordinates of this thread (4 elements per operand plane)
+  int a_k[4], a_m[4], b_k[4], b_n[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    if (AKC) { a_k[r] = tid & 15; a_m[r] = (tid >> 4) + 16 * r; }
+    else     { a_m[r] = tid & 63; a_k[r] = (tid >> 6) + 4 * r; }
+    if (BKC) { b_k[r] = tid & 15; b_n[r] = (tid >> 4) + 16 * r; }
+    else     { b_n[r] = tid & 63; b_k[r] = (tid >> 6) + 4 * r; }
+  }
 
-  for (int64_t b = blockIdx.y; b < g.batch; b += gridDim.y) {
+  int64_t kbeg = 0, kend = g.K, b0 = blockIdx.y, bstep = gridDim.y;
+  if (g.splitk > 1) {
+    kbeg = (int64_t)blockIdx.y * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    b0 = 0;
+    bstep = 1;
+  }
+  for (int64_t b = b0; b < g.batch; b += bstep) {
     const double* Ar = g.ar + b * g.asb;
     const double* Ai = AC ? g.ai + b * g.asb : nullptr;
     const double* Br = g.br + b * g.bsb;
     const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
     d4 accr[2][2], acci[2][2];
+#pragma unroll
     for (int x = 0; x < 2; ++x)
+#pragma unroll
       for (int y = 0; y < 2; ++y) {
         accr[x][y] = d4{0.0, 0.0, 0.0, 0.0};
         acci[x][y] = d4{0.0, 0.0, 0.0, 0.0};
       }
-    for (int64_t k0 = 0; k0 < g.K; k0 += BK) {
-      // ---- stage A
+    double pa_r[4], pa_i[4], pb_r[4], pb_i[4];
+    auto fetch = [&](int64_t k0) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int kk, mm;
-        if (AKC) { kk = tid & 15; mm = (tid >> 4) + 16 * r; }
-        else     { mm = tid & 63; kk = (tid >> 6) + 4 * r; }
-        const int64_t gm = m0 + mm, gk = k0 + kk;
-        double vr = 0.0, vi = 0.0;
-        if (gm < g.M && gk < g.K) {
+        const int64_t gm = m0 + a_m[r], gk = k0 + a_k[r];
+        pa_r[r] = 0.0;
+        pa_i[r] = 0.0;
+        if (gm < g.M && gk < kend) {
           const int64_t o = gm * g.asm_ + gk * g.ask;
-          vr = Ar[o];
-          if (AC) vi = Ai[o];
+          pa_r[r] = Ar[o];
+          if (AC) pa_i[r] = Ai[o];
         }
-        sa_r[kk][mm] = vr;
-        if (AC) sa_i[kk][mm] = vi;
+        const int64_t gn = n0 + b_n[r], gk2 = k0 + b_k[r];
+        pb_r[r] = 0.0;
+        pb_i[r] = 0.0;
+        if (gn < g.N && gk2 < kend) {
+          const int64_t o = gk2 * g.bsk + gn * g.bsn;
+          pb_r[r] = Br[o];
+          if (BC) pb_i[r] = Bi[o];
+        }
       }
-      // ---- stage B
+    };
+    auto stage = [&](int buf) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        int kk, nn;
-        if (BKC) { kk = tid & 15; nn = (tid >> 4) + 16 * r; }
-        else     { nn = tid & 63; kk = (tid >> 6) + 4 * r; }
-        const int64_t gn = n0 + nn, gk = k0 + kk;
-        double vr = 0.0, vi = 0.0;
-        if (gn < g.N && gk < g.K) {
-          const int64_t o = gk * g.bsk + gn * g.bsn;
-          vr = Br[o];
-          if (BC) vi = Bi[o];
-        }
-        sb_r[kk][nn] = vr;
-        if (BC) sb_i[kk][nn] = vi;
+        sa_r[buf][a_k[r]][a_m[r]] = pa_r[r];
+        if (AC) sa_i[buf][a_k[r]][a_m[r]] = pa_i[r];
+        sb_r[buf][b_k[r]][b_n[r]] = pb_r[r];
+        if (BC) sb_i[buf][b_k[r]][b_n[r]] = pb_i[r];
       }
-      __syncthreads();
+    };
+    if (kbeg < kend) {
+      fetch(kbeg);
+      stage(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) fetch(k0 + BK);
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         double a_r[2], a_i[2], b_r[2], b_i[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          a_r[x] = sa_r[kr][wm * 32 + x * 16 + (lane & 15)];
-          a_i[x] = AC ? sa_i[kr][wm * 32 + x * 16 + (lane & 15)] : 0.0;
-          b_r[x] = sb_r[kr][wn * 32 + x * 16 + (lane & 15)];
-          b_i[x] = BC ? sb_i[kr][wn * 32 + x * 16 + (lane & 15)] : 0.0;
+          a_r[x] = sa_r[buf][kr][wm * 32 + x * 16 + (lane & 15)];
+          a_i[x] = AC ? sa_i[buf][kr][wm * 32 + x * 16 + (lane & 15)] : 0.0;
+          b_r[x] = sb_r[buf][kr][wn * 32 + x * 16 + (lane & 15)];
+          b_i[x] = BC ? sb_i[buf][kr][wn * 32 + x * 16 + (lane & 15)] : 0.0;
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -127,12 +156,16 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
             }
           }
       }
+      if (more) stage(buf ^ 1);
       __syncthreads();
+      buf ^= 1;
     }
     // ---- epilogue: for the f64 16x16x4 MFMA, accumulator register r of a lane
     // holds C[4*r + lane/16][lane % 16] of its 16x16 block
-    double* Cr = g.cr + b * g.csb;
-    double* Ci = (AC || BC) ? g.ci + b * g.csb : nullptr;
+    const bool split = g.splitk > 1;
+    double* Cr = split ? g.pr + (int64_t)blockIdx.y * g.M * g.N : g.cr + b * g.csb;
+    double* Ci = (AC || BC) ? (split ? g.pi + (int64_t)blockIdx.y * g.M * g.N : g.ci + b * g.csb) : nullptr;
+    const int64_t sm = split ? g.N : g.csm, sn = split ? 1 : g.csn;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -142,17 +175,45 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
           const int64_t gm = m0 + wm * 32 + x * 16 + 4 * r + (lane >> 4);
           const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
           if (gm < g.M && gn < g.N) {
-            const int64_t o = gm * g.csm + gn * g.csn;
-            double vr = g.alpha * accr[x][y][r];
-            if (g.beta) vr += Cr[o];
-            Cr[o] = vr;
-            if (AC || BC) {
-              double vi = g.alpha * acci[x][y][r];
-              if (g.beta) vi += Ci[o];
-              Ci[o] = vi;
+            const int64_t o = gm * sm + gn * sn;
+            if (split) {
+              Cr[o] = accr[x][y][r];
+              if (AC || BC) Ci[o] = acci[x][y][r];
+            } else {
+              double vr = g.alpha * accr[x][y][r];
+              if (g.beta) vr += Cr[o];
+              Cr[o] = vr;
+              if (AC || BC) {
+                double vi = g.alpha * acci[x][y][r];
+                if (g.beta) vi += Ci[o];
+                Ci[o] = vi;
+              }
             }
           }
         }
+  }
+}
+
+// C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic).
+__global__ __launch_bounds__(256) void splitk_reduce(GemmArgs g, int cplx) {
+  const int64_t total = g.M * g.N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < g.splitk; ++s) {
+      sr += g.pr[s * total + t];
+      if (cplx) si += g.pi[s * total + t];
+    }
+    const int64_t m = t / g.N, n = t - m * g.N;
+    const int64_t o = m * g.csm + n * g.csn;
+    double vr = g.alpha * sr;
+    if (g.beta) vr += g.cr[o];
+    g.cr[o] = vr;
+    if (cplx) {
+      double vi = g.alpha * si;
+      if (g.beta) vi += g.ci[o];
+      g.ci[o] = vi;
+    }
   }
 }
 
@@ -462,12 +523,22 @@ class HipBackend : public Backend {
     g.beta = op.beta;
     g.tiles_m = (op.M + BM - 1) / BM;
     g.tiles_n = (op.N + BN - 1) / BN;
+    g.splitk = 1;
+    g.kchunk = op.K;
+    g.pr = g.pi = nullptr;
+    const bool cplx = op.a_im != nullptr || op.b_im != nullptr;
+    if (op.splitk > 1 && op.partial && op.batch == 1) {
+      g.kchunk = ((op.K + op.splitk - 1) / op.splitk + BK - 1) / BK * BK;
+      g.splitk = (int)((op.K + g.kchunk - 1) / g.kchunk);
+      g.pr = op.partial;
+      g.pi = cplx ? op.partial + (int64_t)g.splitk * op.M * op.N : nullptr;
+    }
     const int64_t tiles = g.tiles_m * g.tiles_n;
     if (tiles > 0x7fffffffLL) {
       set_err("gemm: too many tiles");
       return;
     }
-    dim3 grid((unsigned)tiles, (unsigned)std::min<int64_t>(op.batch, 65535));
+    dim3 grid((unsigned)tiles, (unsigned)(g.splitk > 1 ? g.splitk : std::min<int64_t>(op.batch, 65535)));
     begin();
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
@@ -484,6 +555,10 @@ class HipBackend : public Backend {
     else RTEOM_GEMM(false, false);
 #undef RTEOM_GEMM
     launched("gemm_f64");
+    if (g.splitk > 1) {
+      splitk_reduce<<<grid_for(op.M * op.N), 256, 0, stream_>>>(g, cplx ? 1 : 0);
+      launched("splitk_reduce");
+    }
     end();
   }
 

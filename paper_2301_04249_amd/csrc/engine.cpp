@@ -6,6 +6,11 @@
 
 namespace rteom {
 
+namespace {
+constexpr int64_t kTargetGroups = 512;   // ~2 work-groups per compute unit
+constexpr int64_t kMinSplitK = 256;      // shortest K chunk worth a work-group
+}  // namespace
+
 View make_view(double* re, double* im, std::initializer_list<int64_t> dims) {
   View v;
   v.re = re;
@@ -317,6 +322,18 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   op.alpha = alpha;
   op.beta = ctemp ? 0 : beta;
   op.prec = prec;
+  // Few output tiles and a long sum: cut K so that the device has enough work-groups.
+  {
+    const int64_t tiles = ((op.M + 63) / 64) * ((op.N + 63) / 64) * op.batch;
+    if (op.batch == 1 && tiles < kTargetGroups && op.K >= 2 * kMinSplitK) {
+      int64_t s = std::min<int64_t>((kTargetGroups + tiles - 1) / tiles, op.K / kMinSplitK);
+      s = std::min<int64_t>(s, 256);
+      if (s > 1) {
+        op.splitk = static_cast<int>(s);
+        op.partial = scratch->take((cplx_out ? 2 : 1) * s * op.M * op.N);
+      }
+    }
+  }
   (void)group_size;
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;

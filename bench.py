@@ -66,7 +66,19 @@ def main(argv=None):
     ap.add_argument("--workload", default="formaldehyde", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (HBM counter calibration) and exit")
     args = ap.parse_args(argv)
+    if args.copy_probe:
+        import torch
+        n = args.copy_probe // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8}))
+        return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build measures one GPU only (single-GPU hot path); run with --gpus 1",
               file=sys.stderr)

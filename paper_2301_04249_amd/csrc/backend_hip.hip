@@ -40,6 +40,7 @@ struct GemmArgs {
   int splitk;
   int64_t kchunk;             // K elements per split (multiple of BK)
   double* pr; double* pi;     // partials [splitk][M][N]
+  int m_fast;                 // logical tile order: row tiles fastest (B is the larger operand)
 };
 
 // Operand tiles are staged k-major in LDS ([BK][BM] for A, [BK][BN] for B) so
@@ -56,8 +57,17 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  const int64_t tile = blockIdx.x;
-  const int64_t tm = tile / g.tiles_n, tn = tile % g.tiles_n;
+  // Work-groups are dispatched round-robin over the 8 XCDs.  Give each XCD a
+  // contiguous range of logical tiles, ordered so that neighbours share the
+  // larger operand's tile and reuse it from that XCD's L2.
+  int64_t tm, tn;
+  {
+    const int64_t nt = g.tiles_m * g.tiles_n, bid = blockIdx.x;
+    const int64_t q = nt / 8, r = nt % 8, xcd = bid % 8, slot = bid / 8;
+    const int64_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    if (g.m_fast) { tm = logical % g.tiles_m; tn = logical / g.tiles_m; }
+    else          { tn = logical % g.tiles_n; tm = logical / g.tiles_n; }
+  }
   const int64_t m0 = tm * BM, n0 = tn * BN;
   // staging coordinates of this thread (4 elements per operand plane)
   int a_k[4], a_m[4], b_k[4], b_n[4];
@@ -191,6 +201,40 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
             }
           }
         }
+  }
+}
+
+// Short sums (K <= 16): one output element per thread on the vector units,
+// threads ordered along the output's unit-stride dimension.
+template <bool AC, bool BC>
+__global__ __launch_bounds__(256) void gemm_smallk(GemmArgs g, int n_inner) {
+  const int64_t total = g.batch * g.M * g.N;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
+    int64_t m, n, b;
+    if (n_inner) { n = t % g.N; int64_t r = t / g.N; m = r % g.M; b = r / g.M; }
+    else         { m = t % g.M; int64_t r = t / g.M; n = r % g.N; b = r / g.N; }
+    const double* A = g.ar + b * g.asb + m * g.asm_;
+    const double* Ai = AC ? g.ai + b * g.asb + m * g.asm_ : nullptr;
+    const double* B = g.br + b * g.bsb + n * g.bsn;
+    const double* Bi = BC ? g.bi + b * g.bsb + n * g.bsn : nullptr;
+    double sr = 0.0, si = 0.0;
+    for (int64_t k = 0; k < g.K; ++k) {
+      const double ar = A[k * g.ask], br = B[k * g.bsk];
+      const double ai = AC ? Ai[k * g.ask] : 0.0, bi = BC ? Bi[k * g.bsk] : 0.0;
+      sr += ar * br;
+      if (AC && BC) sr -= ai * bi;
+      if (AC || BC) si += (AC ? ai * br : 0.0) + (BC ? ar * bi : 0.0);
+    }
+    const int64_t o = b * g.csb + m * g.csm + n * g.csn;
+    double vr = g.alpha * sr;
+    if (g.beta) vr += g.cr[o];
+    g.cr[o] = vr;
+    if (AC || BC) {
+      double vi = g.alpha * si;
+      if (g.beta) vi += g.ci[o];
+      g.ci[o] = vi;
+    }
   }
 }
 
@@ -527,6 +571,20 @@ class HipBackend : public Backend {
     g.kchunk = op.K;
     g.pr = g.pi = nullptr;
     const bool cplx = op.a_im != nullptr || op.b_im != nullptr;
+    if (op.K <= 16) {
+      const int n_inner = std::llabs(op.c_sn) <= std::llabs(op.c_sm) ? 1 : 0;
+      const int64_t total = op.batch * op.M * op.N;
+      begin();
+      if (op.a_im && op.b_im) gemm_smallk<true, true><<<grid_for(total), 256, 0, stream_>>>(g, n_inner);
+      else if (op.a_im) gemm_smallk<true, false><<<grid_for(total), 256, 0, stream_>>>(g, n_inner);
+      else if (op.b_im) gemm_smallk<false, true><<<grid_for(total), 256, 0, stream_>>>(g, n_inner);
+      else gemm_smallk<false, false><<<grid_for(total), 256, 0, stream_>>>(g, n_inner);
+      launched("gemm_smallk");
+      end();
+      return;
+    }
+    // the larger operand is reused by neighbouring logical tiles
+    g.m_fast = (op.K * op.N * (op.b_im ? 2 : 1) >= op.M * op.K * (op.a_im ? 2 : 1)) ? 1 : 0;
     if (op.splitk > 1 && op.partial && op.batch == 1) {
       g.kchunk = ((op.K + op.splitk - 1) / op.splitk + BK - 1) / BK * BK;
       g.splitk = (int)((op.K + g.kchunk - 1) / g.kchunk);

@@ -7,8 +7,9 @@
 namespace rteom {
 
 namespace {
-constexpr int64_t kTargetGroups = 512;   // ~2 work-groups per compute unit
-constexpr int64_t kMinSplitK = 256;      // shortest K chunk worth a work-group
+constexpr int64_t kComputeUnits = 256;   // MI355X
+constexpr int64_t kMinSplitK = 128;      // shortest K chunk worth a work-group
+constexpr int64_t kSmallK = 16;          // sums this short run on the vector units
 }  // namespace
 
 View make_view(double* re, double* im, std::initializer_list<int64_t> dims) {
@@ -322,19 +323,28 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   op.alpha = alpha;
   op.beta = ctemp ? 0 : beta;
   op.prec = prec;
-  // Few output tiles and a long sum: cut K so that the device has enough work-groups.
-  {
-    const int64_t tiles = ((op.M + 63) / 64) * ((op.N + 63) / 64) * op.batch;
-    if (op.batch == 1 && tiles < kTargetGroups && op.K >= 2 * kMinSplitK) {
-      int64_t s = std::min<int64_t>((kTargetGroups + tiles - 1) / tiles, op.K / kMinSplitK);
-      s = std::min<int64_t>(s, 256);
-      if (s > 1) {
-        op.splitk = static_cast<int>(s);
-        op.partial = scratch->take((cplx_out ? 2 : 1) * s * op.M * op.N);
+  // Split K when that fills the device better: choose the factor whose work-group
+  // count wastes the least of the last round over the compute units.
+  if (op.batch == 1 && op.K > kSmallK) {
+    const int64_t tiles = ((op.M + 63) / 64) * ((op.N + 63) / 64);
+    double best = 0.0;
+    int64_t best_s = 1;
+    for (int64_t s = 1; s <= 64 && (s == 1 || op.K / s >= kMinSplitK); ++s) {
+      const int64_t groups = tiles * s;
+      const int64_t rounds = (groups + kComputeUnits - 1) / kComputeUnits;
+      const double use = static_cast<double>(groups) / static_cast<double>(rounds * kComputeUnits);
+      if (use > best + 0.05) {
+        best = use;
+        best_s = s;
       }
     }
+    // bound the partial-sum buffer
+    while (best_s > 1 && best_s * op.M * op.N * (cplx_out ? 2 : 1) * 8 > (int64_t(1) << 30)) --best_s;
+    if (best_s > 1) {
+      op.splitk = static_cast<int>(best_s);
+      op.partial = scratch->take((cplx_out ? 2 : 1) * best_s * op.M * op.N);
+    }
   }
-  (void)group_size;
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
   flops += f;

@@ -64,7 +64,7 @@ def main(argv=None):
     ap.add_argument("--steps", type=int, default=4)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="formaldehyde", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="fp64", choices=["fp64"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (HBM counter calibration) and exit")
@@ -128,7 +128,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 update", "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}[args.prec],
         "data": "synthetic (seeded eps and Cholesky vectors of the stated shape)",
         "config": {"workload": work["desc"], "passes_per_step": work["passes"], "residuals_timed": n_res,
                    "flops_per_residual": flops_res, "s_per_residual": (t1 - t0) / n_res},

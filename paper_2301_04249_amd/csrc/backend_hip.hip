@@ -1,10 +1,14 @@
 // gfx950 (MI355X) kernels of the RT-EOM-CCSD engine and the HIP backend.
 //
-//  gemm_f64   complex/real GEMM on the f64 matrix cores
-//             (v_mfma_f64_16x16x4f64), 64x64 output tile per 256-thread
-//             workgroup, operands staged through LDS.  Complex operands are
-//             planar; a complex x complex product is four real MFMA products
-//             per fragment, complex x real two.
+//  gemm_mfma  complex/real GEMM on the matrix cores in float64
+//             (v_mfma_f64_16x16x4f64) or float32 (v_mfma_f32_16x16x4f32),
+//             64x64 output tile per 256-thread work-group, operands staged
+//             through LDS.  Complex operands are planar; a complex x complex
+//             product is four real MFMA products per fragment, complex x real
+//             two.  Split-K and an XCD-aware tile order fill the 256 CUs.
+//  gemm_bf16x3  the same product with bf16 hi/lo operands, three
+//             v_mfma_f32_16x16x32_bf16 products per real product.
+//  gemm_smallk  sums of K <= 16 on the vector ALUs.
 //  permute    strided tensor copy / accumulate / scale (HBM bound).
 //  update     fused trapezoid update of all amplitudes with the per-spin masks,
 //             the optional diagonal map and a max-|change| reduction.
@@ -25,6 +29,8 @@ namespace rteom {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
 constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
 constexpr int kThreads = 256;
@@ -47,12 +53,31 @@ struct GemmArgs {
 // that the MFMA fragment reads (row = lane % 16, k = lane / 16) are unit stride
 // across lanes.  The next K tile is loaded into registers while the current one
 // is multiplied, into the other of two LDS buffers: one barrier per K tile.
-template <bool AC, bool BC, bool AKC, bool BKC>
-__global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
-  __shared__ double sa_r[2][BK][BM + PAD];
-  __shared__ double sa_i[AC ? 2 : 1][AC ? BK : 1][BM + PAD];
-  __shared__ double sb_r[2][BK][BN + PAD];
-  __shared__ double sb_i[BC ? 2 : 1][BC ? BK : 1][BN + PAD];
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef d4 acc_t;
+  static __device__ inline acc_t mma(double a, double b, acc_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  // accumulator register r of a lane holds row 4*r + lane/16 of the 16x16 block
+  static __device__ inline int row(int lane, int r) { return 4 * r + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+  typedef f4 acc_t;
+  static __device__ inline acc_t mma(float a, float b, acc_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // accumulator register r of a lane holds row 4*(lane/16) + r of the 16x16 block
+  static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
+};
+
+template <typename T, bool AC, bool BC, bool AKC, bool BKC>
+__global__ __launch_bounds__(kThreads) void gemm_mfma(GemmArgs g) {
+  typedef typename Mfma<T>::acc_t acc_t;
+  __shared__ T sa_r[2][BK][BM + PAD];
+  __shared__ T sa_i[AC ? 2 : 1][AC ? BK : 1][BM + PAD];
+  __shared__ T sb_r[2][BK][BN + PAD];
+  __shared__ T sb_i[BC ? 2 : 1][BC ? BK : 1][BN + PAD];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -91,13 +116,13 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
     const double* Ai = AC ? g.ai + b * g.asb : nullptr;
     const double* Br = g.br + b * g.bsb;
     const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
-    d4 accr[2][2], acci[2][2];
+    acc_t accr[2][2], acci[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
       for (int y = 0; y < 2; ++y) {
-        accr[x][y] = d4{0.0, 0.0, 0.0, 0.0};
-        acci[x][y] = d4{0.0, 0.0, 0.0, 0.0};
+        accr[x][y] = acc_t{0, 0, 0, 0};
+        acci[x][y] = acc_t{0, 0, 0, 0};
       }
     double pa_r[4], pa_i[4], pb_r[4], pb_i[4];
     auto fetch = [&](int64_t k0) {
@@ -124,10 +149,10 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
     auto stage = [&](int buf) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        sa_r[buf][a_k[r]][a_m[r]] = pa_r[r];
-        if (AC) sa_i[buf][a_k[r]][a_m[r]] = pa_i[r];
-        sb_r[buf][b_k[r]][b_n[r]] = pb_r[r];
-        if (BC) sb_i[buf][b_k[r]][b_n[r]] = pb_i[r];
+        sa_r[buf][a_k[r]][a_m[r]] = (T)pa_r[r];
+        if (AC) sa_i[buf][a_k[r]][a_m[r]] = (T)pa_i[r];
+        sb_r[buf][b_k[r]][b_n[r]] = (T)pb_r[r];
+        if (BC) sb_i[buf][b_k[r]][b_n[r]] = (T)pb_i[r];
       }
     };
     if (kbeg < kend) {
@@ -142,27 +167,27 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
 #pragma unroll
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
-        double a_r[2], a_i[2], b_r[2], b_i[2];
+        T a_r[2], a_i[2], b_r[2], b_i[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
           a_r[x] = sa_r[buf][kr][wm * 32 + x * 16 + (lane & 15)];
-          a_i[x] = AC ? sa_i[buf][kr][wm * 32 + x * 16 + (lane & 15)] : 0.0;
+          a_i[x] = AC ? sa_i[buf][kr][wm * 32 + x * 16 + (lane & 15)] : (T)0;
           b_r[x] = sb_r[buf][kr][wn * 32 + x * 16 + (lane & 15)];
-          b_i[x] = BC ? sb_i[buf][kr][wn * 32 + x * 16 + (lane & 15)] : 0.0;
+          b_i[x] = BC ? sb_i[buf][kr][wn * 32 + x * 16 + (lane & 15)] : (T)0;
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
-            accr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_r[y], accr[x][y], 0, 0, 0);
+            accr[x][y] = Mfma<T>::mma(a_r[x], b_r[y], accr[x][y]);
             if (AC && BC) {
-              accr[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(-a_i[x], b_i[y], accr[x][y], 0, 0, 0);
-              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_i[y], acci[x][y], 0, 0, 0);
-              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], acci[x][y], 0, 0, 0);
+              accr[x][y] = Mfma<T>::mma(-a_i[x], b_i[y], accr[x][y]);
+              acci[x][y] = Mfma<T>::mma(a_r[x], b_i[y], acci[x][y]);
+              acci[x][y] = Mfma<T>::mma(a_i[x], b_r[y], acci[x][y]);
             } else if (AC) {
-              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_i[x], b_r[y], acci[x][y], 0, 0, 0);
+              acci[x][y] = Mfma<T>::mma(a_i[x], b_r[y], acci[x][y]);
             } else if (BC) {
-              acci[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_r[x], b_i[y], acci[x][y], 0, 0, 0);
+              acci[x][y] = Mfma<T>::mma(a_r[x], b_i[y], acci[x][y]);
             }
           }
       }
@@ -170,8 +195,7 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
       __syncthreads();
       buf ^= 1;
     }
-    // ---- epilogue: for the f64 16x16x4 MFMA, accumulator register r of a lane
-    // holds C[4*r + lane/16][lane % 16] of its 16x16 block
+    // ---- epilogue (row of accumulator register r: Mfma<T>::row)
     const bool split = g.splitk > 1;
     double* Cr = split ? g.pr + (int64_t)blockIdx.y * g.M * g.N : g.cr + b * g.csb;
     double* Ci = (AC || BC) ? (split ? g.pi + (int64_t)blockIdx.y * g.M * g.N : g.ci + b * g.csb) : nullptr;
@@ -182,19 +206,200 @@ __global__ __launch_bounds__(kThreads) void gemm_f64(GemmArgs g) {
       for (int y = 0; y < 2; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * 32 + x * 16 + 4 * r + (lane >> 4);
+          const int64_t gm = m0 + wm * 32 + x * 16 + Mfma<T>::row(lane, r);
           const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * sm + gn * sn;
             if (split) {
-              Cr[o] = accr[x][y][r];
-              if (AC || BC) Ci[o] = acci[x][y][r];
+              Cr[o] = (double)accr[x][y][r];
+              if (AC || BC) Ci[o] = (double)acci[x][y][r];
             } else {
-              double vr = g.alpha * accr[x][y][r];
+              double vr = g.alpha * (double)accr[x][y][r];
               if (g.beta) vr += Cr[o];
               Cr[o] = vr;
               if (AC || BC) {
-                double vi = g.alpha * acci[x][y][r];
+                double vi = g.alpha * (double)acci[x][y][r];
+                if (g.beta) vi += Ci[o];
+                Ci[o] = vi;
+              }
+            }
+          }
+        }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// bf16 x 3 split precision: every float64 operand x is split into
+// hi = bf16(x) and lo = bf16(x - hi); a*b ~ ah*bh + ah*bl + al*bh (the lo*lo
+// term, ~2^-16 relative, is dropped), accumulated in float32 on the
+// v_mfma_f32_16x16x32_bf16 matrix cores.  Tile 64x64x32, one LDS buffer.
+constexpr int BKH = 32, PADH = 8;
+
+__device__ inline unsigned short bf16_rne(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+
+__device__ inline void split_bf16(double x, unsigned short& hi, unsigned short& lo) {
+  hi = bf16_rne((float)x);
+  const float fh = __uint_as_float(((unsigned)hi) << 16);
+  lo = bf16_rne((float)(x - (double)fh));
+}
+
+__device__ inline bf8 ld8(const unsigned short* p) { return *reinterpret_cast<const bf8*>(p); }
+
+__device__ inline bf8 neg8(bf8 v) {
+  typedef unsigned short u8v __attribute__((ext_vector_type(8)));
+  u8v u = __builtin_bit_cast(u8v, v);
+  u ^= (unsigned short)0x8000;
+  return __builtin_bit_cast(bf8, u);
+}
+
+__device__ inline f4 mma3(bf8 ah, bf8 al, bf8 bh, bf8 bl, f4 c) {
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+template <bool AC, bool BC, bool AKC, bool BKC>
+__global__ __launch_bounds__(kThreads) void gemm_bf16x3(GemmArgs g) {
+  // [row][k] with k contiguous: each lane reads 8 consecutive k values
+  __shared__ __attribute__((aligned(16))) unsigned short arh[BM][BKH + PADH], arl[BM][BKH + PADH];
+  __shared__ __attribute__((aligned(16))) unsigned short aih[AC ? BM : 1][BKH + PADH], ail[AC ? BM : 1][BKH + PADH];
+  __shared__ __attribute__((aligned(16))) unsigned short brh[BN][BKH + PADH], brl[BN][BKH + PADH];
+  __shared__ __attribute__((aligned(16))) unsigned short bih[BC ? BN : 1][BKH + PADH], bil[BC ? BN : 1][BKH + PADH];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t tm, tn;
+  {
+    const int64_t nt = g.tiles_m * g.tiles_n, bid = blockIdx.x;
+    const int64_t q = nt / 8, r = nt % 8, xcd = bid % 8, slot = bid / 8;
+    const int64_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+    if (g.m_fast) { tm = logical % g.tiles_m; tn = logical / g.tiles_m; }
+    else          { tn = logical % g.tiles_n; tm = logical / g.tiles_n; }
+  }
+  const int64_t m0 = tm * BM, n0 = tn * BN;
+  int a_k[8], a_m[8], b_k[8], b_n[8];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    if (AKC) { a_k[r] = tid & 31; a_m[r] = (tid >> 5) + 8 * r; }
+    else     { a_m[r] = tid & 63; a_k[r] = (tid >> 6) + 4 * r; }
+    if (BKC) { b_k[r] = tid & 31; b_n[r] = (tid >> 5) + 8 * r; }
+    else     { b_n[r] = tid & 63; b_k[r] = (tid >> 6) + 4 * r; }
+  }
+  int64_t kbeg = 0, kend = g.K, b0 = blockIdx.y, bstep = gridDim.y;
+  if (g.splitk > 1) {
+    kbeg = (int64_t)blockIdx.y * g.kchunk;
+    kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+    b0 = 0;
+    bstep = 1;
+  }
+  for (int64_t b = b0; b < g.batch; b += bstep) {
+    const double* Ar = g.ar + b * g.asb;
+    const double* Ai = AC ? g.ai + b * g.asb : nullptr;
+    const double* Br = g.br + b * g.bsb;
+    const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
+    f4 accr[2][2], acci[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) {
+        accr[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        acci[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    double pa_r[8], pa_i[8], pb_r[8], pb_i[8];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        const int64_t gm = m0 + a_m[r], gk = k0 + a_k[r];
+        pa_r[r] = 0.0;
+        pa_i[r] = 0.0;
+        if (gm < g.M && gk < kend) {
+          const int64_t o = gm * g.asm_ + gk * g.ask;
+          pa_r[r] = Ar[o];
+          if (AC) pa_i[r] = Ai[o];
+        }
+        const int64_t gn = n0 + b_n[r], gk2 = k0 + b_k[r];
+        pb_r[r] = 0.0;
+        pb_i[r] = 0.0;
+        if (gn < g.N && gk2 < kend) {
+          const int64_t o = gk2 * g.bsk + gn * g.bsn;
+          pb_r[r] = Br[o];
+          if (BC) pb_i[r] = Bi[o];
+        }
+      }
+    };
+    auto stage = [&]() {
+#pragma unroll
+      for (int r = 0; r < 8; ++r) {
+        split_bf16(pa_r[r], arh[a_m[r]][a_k[r]], arl[a_m[r]][a_k[r]]);
+        if (AC) split_bf16(pa_i[r], aih[a_m[r]][a_k[r]], ail[a_m[r]][a_k[r]]);
+        split_bf16(pb_r[r], brh[b_n[r]][b_k[r]], brl[b_n[r]][b_k[r]]);
+        if (BC) split_bf16(pb_i[r], bih[b_n[r]][b_k[r]], bil[b_n[r]][b_k[r]]);
+      }
+    };
+    if (kbeg < kend) fetch(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BKH) {
+      stage();
+      __syncthreads();
+      if (k0 + BKH < kend) fetch(k0 + BKH);
+      const int kk = (lane >> 4) * 8;
+      bf8 xrh[2], xrl[2], xih[2], xil[2], yrh[2], yrl[2], yih[2], yil[2];
+#pragma unroll
+      for (int x = 0; x < 2; ++x) {
+        const int row = wm * 32 + x * 16 + (lane & 15);
+        xrh[x] = ld8(&arh[row][kk]);
+        xrl[x] = ld8(&arl[row][kk]);
+        if (AC) { xih[x] = ld8(&aih[row][kk]); xil[x] = ld8(&ail[row][kk]); }
+        const int col = wn * 32 + x * 16 + (lane & 15);
+        yrh[x] = ld8(&brh[col][kk]);
+        yrl[x] = ld8(&brl[col][kk]);
+        if (BC) { yih[x] = ld8(&bih[col][kk]); yil[x] = ld8(&bil[col][kk]); }
+      }
+#pragma unroll
+      for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+          accr[x][y] = mma3(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
+          if (AC && BC) {
+            accr[x][y] = mma3(neg8(xih[x]), neg8(xil[x]), yih[y], yil[y], accr[x][y]);
+            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+          } else if (AC) {
+            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+          } else if (BC) {
+            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+          }
+        }
+      __syncthreads();
+    }
+    const bool split = g.splitk > 1;
+    double* Cr = split ? g.pr + (int64_t)blockIdx.y * g.M * g.N : g.cr + b * g.csb;
+    double* Ci = (AC || BC) ? (split ? g.pi + (int64_t)blockIdx.y * g.M * g.N : g.ci + b * g.csb) : nullptr;
+    const int64_t sm = split ? g.N : g.csm, sn = split ? 1 : g.csn;
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = m0 + wm * 32 + x * 16 + 4 * (lane >> 4) + r;
+          const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
+          if (gm < g.M && gn < g.N) {
+            const int64_t o = gm * sm + gn * sn;
+            if (split) {
+              Cr[o] = (double)accr[x][y][r];
+              if (AC || BC) Ci[o] = (double)acci[x][y][r];
+            } else {
+              double vr = g.alpha * (double)accr[x][y][r];
+              if (g.beta) vr += Cr[o];
+              Cr[o] = vr;
+              if (AC || BC) {
+                double vi = g.alpha * (double)acci[x][y][r];
                 if (g.beta) vi += Ci[o];
                 Ci[o] = vi;
               }
@@ -483,6 +688,29 @@ __global__ void cumulant_kernel(double* c, int64_t k, const double* ep, const do
   }
 }
 
+template <typename T, bool AC, bool BC>
+void launch_mfma(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (akc && bkc) gemm_mfma<T, AC, BC, true, true><<<grid, kThreads, 0, st>>>(g);
+  else if (akc) gemm_mfma<T, AC, BC, true, false><<<grid, kThreads, 0, st>>>(g);
+  else if (bkc) gemm_mfma<T, AC, BC, false, true><<<grid, kThreads, 0, st>>>(g);
+  else gemm_mfma<T, AC, BC, false, false><<<grid, kThreads, 0, st>>>(g);
+}
+
+template <bool AC, bool BC>
+void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (akc && bkc) gemm_bf16x3<AC, BC, true, true><<<grid, kThreads, 0, st>>>(g);
+  else if (akc) gemm_bf16x3<AC, BC, true, false><<<grid, kThreads, 0, st>>>(g);
+  else if (bkc) gemm_bf16x3<AC, BC, false, true><<<grid, kThreads, 0, st>>>(g);
+  else gemm_bf16x3<AC, BC, false, false><<<grid, kThreads, 0, st>>>(g);
+}
+
+template <bool AC, bool BC>
+void launch_prec(int prec, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (prec == 0) launch_mfma<double, AC, BC>(grid, st, g, akc, bkc);
+  else if (prec == 1) launch_mfma<float, AC, BC>(grid, st, g, akc, bkc);
+  else launch_bf16x3<AC, BC>(grid, st, g, akc, bkc);
+}
+
 int grid_for(int64_t n, int per_block = 256) {
   int64_t g = (n + per_block - 1) / per_block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
@@ -554,8 +782,8 @@ class HipBackend : public Backend {
   int64_t energy_partials() const override { return 2 * kEnergyBlocks; }
 
   void gemm(const GemmOp& op) override {
-    if (op.prec != 0) {
-      set_err("only float64 contractions are built into this library");
+    if (op.prec < 0 || op.prec > 2) {
+      set_err("unknown contraction precision");
       return;
     }
     GemmArgs g;
@@ -586,7 +814,7 @@ class HipBackend : public Backend {
     // the larger operand is reused by neighbouring logical tiles
     g.m_fast = (op.K * op.N * (op.b_im ? 2 : 1) >= op.M * op.K * (op.a_im ? 2 : 1)) ? 1 : 0;
     if (op.splitk > 1 && op.partial && op.batch == 1) {
-      g.kchunk = ((op.K + op.splitk - 1) / op.splitk + BK - 1) / BK * BK;
+      g.kchunk = ((op.K + op.splitk - 1) / op.splitk + BKH - 1) / BKH * BKH;
       g.splitk = (int)((op.K + g.kchunk - 1) / g.kchunk);
       g.pr = op.partial;
       g.pi = cplx ? op.partial + (int64_t)g.splitk * op.M * op.N : nullptr;
@@ -600,19 +828,11 @@ class HipBackend : public Backend {
     begin();
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
-#define RTEOM_GEMM(AC, BC)                                                                     \
-  do {                                                                                       \
-    if (akc && bkc) gemm_f64<AC, BC, true, true><<<grid, kThreads, 0, stream_>>>(g);          \
-    else if (akc) gemm_f64<AC, BC, true, false><<<grid, kThreads, 0, stream_>>>(g);           \
-    else if (bkc) gemm_f64<AC, BC, false, true><<<grid, kThreads, 0, stream_>>>(g);           \
-    else gemm_f64<AC, BC, false, false><<<grid, kThreads, 0, stream_>>>(g);                   \
-  } while (0)
-    if (ac && bc) RTEOM_GEMM(true, true);
-    else if (ac) RTEOM_GEMM(true, false);
-    else if (bc) RTEOM_GEMM(false, true);
-    else RTEOM_GEMM(false, false);
-#undef RTEOM_GEMM
-    launched("gemm_f64");
+    if (ac && bc) launch_prec<true, true>(op.prec, grid, stream_, g, akc, bkc);
+    else if (ac) launch_prec<true, false>(op.prec, grid, stream_, g, akc, bkc);
+    else if (bc) launch_prec<false, true>(op.prec, grid, stream_, g, akc, bkc);
+    else launch_prec<false, false>(op.prec, grid, stream_, g, akc, bkc);
+    launched("gemm");
     if (g.splitk > 1) {
       splitk_reduce<<<grid_for(op.M * op.N), 256, 0, stream_>>>(g, cplx ? 1 : 0);
       launched("splitk_reduce");

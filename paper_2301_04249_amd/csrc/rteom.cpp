@@ -139,7 +139,7 @@ struct Context {
     setup_spaces();
     eng.be = be;
     eng.scratch = &arena;
-    eng.prec = opt.prec;
+    eng.prec = RTEOM_FP64;   // integral blocks and Fock matrices: float64, once
     eng.dry = dry;
     const int64_t Q = nq;
     std::vector<int> ext(O);
@@ -271,6 +271,7 @@ struct Context {
   void residual(double* Xs, double* Rs) {
     const int64_t Q = nq;
     const size_t mk = arena.mark();
+    eng.prec = opt.prec;     // the residual's contractions in the requested precision
     eng.flops = 0.0;
     for (double& f : eng.phase_flops) f = 0.0;
     eng.set_phase(kPhaseGemm);
@@ -472,6 +473,7 @@ struct Context {
     }
     res_flops = eng.flops;
     for (int k = 0; k < kNumPhases; ++k) res_phase_flops[k] = eng.phase_flops[k];
+    eng.prec = RTEOM_FP64;
     arena.release(mk);
   }
 

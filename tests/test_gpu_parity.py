@@ -78,3 +78,28 @@ def test_zero_amplitudes_residual_is_driver():
     assert np.abs(r1 - e1).max() < 1e-14
     assert np.abs(r2 - e2).max() < 1e-14
     assert P.energy() == 0
+
+
+@pytest.mark.parametrize("prec,res_tol,c_tol", [("fp32", 1e-5, 1e-6), ("bf16x3", 1e-3, 1e-4)])
+def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol):
+    """float32 and bf16x3 contractions (float64 update and C(t)): residual relative Frobenius
+    error and C(t) max error against the oracle on the tiny workload (40 steps)."""
+    eps, chol = draw_system(TINY, cfg=0)
+    sysm = reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1)
+    P = _prop(eps, chol, 4, 4, 0, 1, prec=prec, fixed_iters=3)
+    t1, t2 = blocks.random_spin_orbital_amplitudes(sysm, 11, scale=0.05)
+    b1, b2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, t1, t2)
+    P.set_amplitudes(b1, b2)
+    r1, r2 = P.residual()
+    e1, e2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, *ccsd.residual(sysm, t1, t2))
+    rel = np.sqrt(np.sum(np.abs(r1 - e1) ** 2) + np.sum(np.abs(r2 - e2) ** 2)) / np.sqrt(
+        np.sum(np.abs(e1) ** 2) + np.sum(np.abs(e2) ** 2))
+    P.close()
+    P = _prop(eps, chol, 4, 4, 0, 1, prec=prec, fixed_iters=3)
+    P.step(0.025, 40)
+    _, c = P.cumulant()
+    ref = propagate.propagate(sysm, 0.025, 40, fixed_iters=3).cumulant
+    cerr = np.abs(c - ref).max()
+    print(f"{prec}: residual rel Frobenius {rel:.3e}, C(t) max abs err {cerr:.3e} (max |C| {np.abs(ref).max():.3e})")
+    assert rel < res_tol
+    assert cerr < c_tol

@@ -10,7 +10,7 @@ import pytest
 import blocks
 from oracle import ccsd, propagate, reference
 from paper_2301_04249_amd import rteom
-from synthetic import Shape, TINY, draw_system
+from synthetic import FORMALDEHYDE, Shape, TINY, draw_system
 
 pytestmark = pytest.mark.gpu
 
@@ -44,15 +44,17 @@ def test_residual_parity(case):
     assert abs(P.energy() - ccsd.energy(sysm, t1, t2)) <= 1e-11 * max(1.0, abs(ccsd.energy(sysm, t1, t2)))
 
 
-@pytest.mark.parametrize("kw", [dict(fixed_iters=3), dict(tol=1e-11), dict(tol=1e-11, fp_map=1)])
-def test_tiny_propagation_parity(kw):
-    """Tiny workload (o=4, v=16 per spin, Q=48, beta core hole, dt=0.025): 40 steps vs the oracle."""
+@pytest.mark.parametrize("kw,steps", [(dict(fixed_iters=3), 200), (dict(tol=1e-11), 40),
+                                      (dict(tol=1e-11, fp_map=1), 40)])
+def test_tiny_propagation_parity(kw, steps):
+    """Tiny workload (o=4, v=16 per spin, Q=48, beta core hole, dt=0.025): C(t) vs the oracle
+    (the full 200-step propagation with fixed passes; 40 steps in the tolerance modes)."""
     eps, chol = draw_system(TINY, cfg=0)
     sysm = reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1)
     P = _prop(eps, chol, 4, 4, 0, 1, **kw)
-    it = P.step(0.025, 40)
+    it = P.step(0.025, steps)
     t, c = P.cumulant()
-    tr = propagate.propagate(sysm, 0.025, 40, fixed_iters=kw.get("fixed_iters"), tol=kw.get("tol", 1e-13),
+    tr = propagate.propagate(sysm, 0.025, steps, fixed_iters=kw.get("fixed_iters"), tol=kw.get("tol", 1e-13),
                              fp_map="denominator" if kw.get("fp_map") else "plain")
     assert np.array_equal(it, tr.iters)
     assert np.abs(c - tr.cumulant).max() < 1e-10
@@ -103,3 +105,28 @@ def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol):
     print(f"{prec}: residual rel Frobenius {rel:.3e}, C(t) max abs err {cerr:.3e} (max |C| {np.abs(ref).max():.3e})")
     assert rel < res_tol
     assert cerr < c_tol
+
+
+def test_formaldehyde_full_size_parity():
+    """The benchmark workload at full size (o=8, v=110 per spin, Q=600, same seed and launch
+    configuration as bench.py): every residual element at seeded amplitudes, then one time step
+    (3 passes) of C(t), against the oracle in lean mode."""
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1)
+    sysm = reference.n_minus_one_reference(eps, chol, 8, 8, 0, 1, lean=True)
+    P = _prop(eps, chol, 8, 8, 0, 1, fixed_iters=3)
+    t1, t2 = blocks.random_spin_orbital_amplitudes(sysm, 17, scale=1e-3)
+    b1, b2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, t1, t2)
+    P.set_amplitudes(b1, b2)
+    r1, r2 = P.residual()
+    e1, e2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, *ccsd.residual(sysm, t1, t2))
+    scale = max(np.abs(e1).max(), np.abs(e2).max())
+    print(f"formaldehyde residual max abs err {max(np.abs(r1 - e1).max(), np.abs(r2 - e2).max()):.3e} (scale {scale:.3e})")
+    assert np.abs(r1 - e1).max() <= 1e-11 * scale
+    assert np.abs(r2 - e2).max() <= 1e-11 * scale
+    P.close()
+    P = _prop(eps, chol, 8, 8, 0, 1, fixed_iters=3)
+    P.step(0.025, 1)
+    _, c = P.cumulant()
+    ref = propagate.propagate(sysm, 0.025, 1, fixed_iters=3).cumulant
+    print(f"formaldehyde C(dt) {ref[1]:.6e} err {abs(c[1] - ref[1]):.3e}")
+    assert abs(c[1] - ref[1]) <= 1e-10 * max(1.0, abs(ref[1]))

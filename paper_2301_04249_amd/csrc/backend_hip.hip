@@ -32,7 +32,7 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-constexpr int BM = 64, BN = 64, BK = 16, PAD = 2;
+constexpr int BM = 64, BN = 64, BK = 16;
 constexpr int kThreads = 256;
 
 struct GemmArgs {
@@ -72,12 +72,19 @@ template <> struct Mfma<float> {
 };
 
 template <typename T, bool AC, bool BC, bool AKC, bool BKC>
-__global__ __launch_bounds__(kThreads) void gemm_mfma(GemmArgs g) {
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_mfma(GemmArgs g) {
   typedef typename Mfma<T>::acc_t acc_t;
-  __shared__ T sa_r[2][BK][BM + PAD];
-  __shared__ T sa_i[AC ? 2 : 1][AC ? BK : 1][BM + PAD];
-  __shared__ T sb_r[2][BK][BN + PAD];
-  __shared__ T sb_i[BC ? 2 : 1][BC ? BK : 1][BN + PAD];
+  // LDS tiles: a k-contiguous operand is kept [row][BK + 1] (odd stride: the
+  // coalesced writes and the fragment reads are both free of bank conflicts),
+  // otherwise [k][row + 16] (the two 16-lane halves of a read hit disjoint banks).
+  constexpr int AR = AKC ? BM : BK, AC_ = AKC ? BK + 1 : BM + 16;
+  constexpr int BR = BKC ? BN : BK, BC_ = BKC ? BK + 1 : BN + 16;
+  __shared__ T sa_r[2][AR][AC_];
+  __shared__ T sa_i[AC ? 2 : 1][AC ? AR : 1][AC_];
+  __shared__ T sb_r[2][BR][BC_];
+  __shared__ T sb_i[BC ? 2 : 1][BC ? BR : 1][BC_];
+  auto A_at = [&](int kk, int mm) -> int { return AKC ? mm * AC_ + kk : kk * AC_ + mm; };
+  auto B_at = [&](int kk, int nn) -> int { return BKC ? nn * BC_ + kk : kk * BC_ + nn; };
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -149,10 +156,10 @@ __global__ __launch_bounds__(kThreads) void gemm_mfma(GemmArgs g) {
     auto stage = [&](int buf) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        sa_r[buf][a_k[r]][a_m[r]] = (T)pa_r[r];
-        if (AC) sa_i[buf][a_k[r]][a_m[r]] = (T)pa_i[r];
-        sb_r[buf][b_k[r]][b_n[r]] = (T)pb_r[r];
-        if (BC) sb_i[buf][b_k[r]][b_n[r]] = (T)pb_i[r];
+        (&sa_r[buf][0][0])[A_at(a_k[r], a_m[r])] = (T)pa_r[r];
+        if (AC) (&sa_i[buf][0][0])[A_at(a_k[r], a_m[r])] = (T)pa_i[r];
+        (&sb_r[buf][0][0])[B_at(b_k[r], b_n[r])] = (T)pb_r[r];
+        if (BC) (&sb_i[buf][0][0])[B_at(b_k[r], b_n[r])] = (T)pb_i[r];
       }
     };
     if (kbeg < kend) {
@@ -170,10 +177,12 @@ __global__ __launch_bounds__(kThreads) void gemm_mfma(GemmArgs g) {
         T a_r[2], a_i[2], b_r[2], b_i[2];
 #pragma unroll
         for (int x = 0; x < 2; ++x) {
-          a_r[x] = sa_r[buf][kr][wm * 32 + x * 16 + (lane & 15)];
-          a_i[x] = AC ? sa_i[buf][kr][wm * 32 + x * 16 + (lane & 15)] : (T)0;
-          b_r[x] = sb_r[buf][kr][wn * 32 + x * 16 + (lane & 15)];
-          b_i[x] = BC ? sb_i[buf][kr][wn * 32 + x * 16 + (lane & 15)] : (T)0;
+          const int ia = A_at(kr, wm * 32 + x * 16 + (lane & 15));
+          const int ib = B_at(kr, wn * 32 + x * 16 + (lane & 15));
+          a_r[x] = (&sa_r[buf][0][0])[ia];
+          a_i[x] = AC ? (&sa_i[buf][0][0])[ia] : (T)0;
+          b_r[x] = (&sb_r[buf][0][0])[ib];
+          b_i[x] = BC ? (&sb_i[buf][0][0])[ib] : (T)0;
         }
 #pragma unroll
         for (int x = 0; x < 2; ++x)

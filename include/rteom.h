@@ -50,6 +50,7 @@ extern "C" {
 #endif
 
 typedef struct rteom_ctx rteom_ctx;
+typedef struct rteom_batch rteom_batch;
 
 typedef enum {
   RTEOM_OK = 0,
@@ -75,7 +76,8 @@ typedef struct {
   int32_t fp_max_iter;     /* pass limit when tolerance driven */
   double fp_tol;           /* max |T^(k+1) - T^(k)| over all amplitudes that ends the passes */
   int32_t dC_include_fT1;  /* 1: dC/dt includes sum f_ia t_ia (Eq. cum_gf3); 0: Eq. dcdt as printed */
-  int32_t reserved0;
+  int32_t reserved0;       /* graph mode: 1 = with fp_fixed_iters > 0 and a non-null stream, each
+                              time step is captured once as a hipGraph and replayed */
   int64_t max_steps;       /* capacity of the device C(t) history (time steps) */
   void* stream;            /* hipStream_t borrowed from the caller; NULL = null stream */
   void* workspace;         /* caller-owned device memory, or NULL (library allocates) */
@@ -147,6 +149,15 @@ rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask);
    residual evaluation (same convention as rteom_residual_flops).  Synchronises the stream. */
 rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops,
                                int64_t* ops);
+
+/* Batch of independent core-hole propagations (Sec. 3: the core-hole simulations "can run
+   simultaneously").  Every context must be in graph mode with fixed passes, on its own
+   stream; the batch borrows them (they must outlive it).  rteom_batch_step advances all of
+   them by n_steps of dt with one graph launch per step: a graph whose independent child
+   nodes are the contexts' captured time steps.  Synchronises on return. */
+rteom_status rteom_batch_create(rteom_batch** batch, int32_t n, rteom_ctx* const* ctxs);
+rteom_status rteom_batch_step(rteom_batch* batch, double dt, int32_t n_steps);
+rteom_status rteom_batch_free(rteom_batch* batch);   /* NULL-safe; leaves the contexts */
 
 /* Release the context (NULL-safe). */
 rteom_status rteom_free(rteom_ctx* ctx);

@@ -124,9 +124,22 @@ class Backend {
   virtual void permute(const PermOp& op) = 0;
   virtual void update(const UpdateOp& op) = 0;
   virtual void energy(const EnergyOp& op) = 0;
-  // C[k+1] = C[k] + i h (E_k + E_{k+1}); e_prev/e_next/c are device (re, im) pairs
-  virtual void cumulant_append(double* c_hist, int64_t k, const double* e_prev,
-                               const double* e_next, double h) = 0;
+  // With k = *step (device): C[k+1] = C[k] + i h (E[k] + e_next), E[k+1] = e_next,
+  // *step = k + 1.  c_hist, e_hist: device (re, im) pairs; e_next: device pair.
+  virtual void cumulant_append(double* c_hist, double* e_hist, const double* e_next,
+                               int64_t* step, double h) = 0;
+  // Stream capture of a fixed sequence of operations into a replayable graph
+  // (returns false where not supported: the caller then issues operations directly).
+  virtual bool begin_capture() { return false; }
+  virtual void* end_capture() { return nullptr; }
+  virtual void launch_graph(void* exec) { (void)exec; }
+  virtual void destroy_graph(void* exec) { (void)exec; }
+  // the captured (not instantiated) graph behind an executable graph
+  virtual void* captured_graph(void* exec) { (void)exec; return nullptr; }
+  // an executable graph whose child nodes are the given captured graphs, with no
+  // dependencies between them (they may run concurrently)
+  virtual void* combine_graphs(void* const* graphs, int n) { (void)graphs; (void)n; return nullptr; }
+  virtual void* stream() { return nullptr; }
   virtual int64_t energy_partials() const = 0;
   virtual void sync() = 0;
   // returns false (and a message) if an asynchronous error has been recorded

@@ -689,11 +689,15 @@ __global__ __launch_bounds__(64) void energy_pass2(EnArgs e, int nparts) {
   if (threadIdx.x == 0) { e.out[0] = ar; e.out[1] = ai; }
 }
 
-__global__ void cumulant_kernel(double* c, int64_t k, const double* ep, const double* en, double h) {
+__global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t* step, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    const double sr = ep[0] + en[0], si = ep[1] + en[1];
+    const int64_t k = *step;
+    const double sr = e[2 * k] + en[0], si = e[2 * k + 1] + en[1];
     c[2 * (k + 1)] = c[2 * k] - h * si;
     c[2 * (k + 1) + 1] = c[2 * k + 1] + h * sr;
+    e[2 * (k + 1)] = en[0];
+    e[2 * (k + 1) + 1] = en[1];
+    *step = k + 1;
   }
 }
 
@@ -731,7 +735,10 @@ class HipBackend : public Backend {
   ~HipBackend() override {
     for (auto& e : done_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : pool_) (void)hipEventDestroy(e);
+    for (auto& g : graphs_) (void)hipGraphDestroy(g);
+    if (own_stream_) (void)hipStreamDestroy(stream_);
   }
+  bool own_stream_ = false;
 
   void set_profile(unsigned mask) override { mask_ = mask; }
   double phase_ms(int ph, int64_t* ops) override {
@@ -898,15 +905,65 @@ class HipBackend : public Backend {
     end();
   }
 
-  void cumulant_append(double* c, int64_t k, const double* ep, const double* en, double h) override {
+  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h) override {
     begin();
-    cumulant_kernel<<<1, 64, 0, stream_>>>(c, k, ep, en, h);
+    cumulant_kernel<<<1, 64, 0, stream_>>>(c, e, en, step, h);
     launched("cumulant");
     end();
   }
 
+  void* stream() override { return stream_; }
+  bool begin_capture() override {
+    if (stream_ == nullptr) return false;   // the legacy null stream cannot be captured
+    capturing_ = true;
+    record(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    return err_.empty();
+  }
+  void* end_capture() override {
+    hipGraph_t graph = nullptr;
+    record(hipStreamEndCapture(stream_, &graph), "hipStreamEndCapture");
+    capturing_ = false;
+    if (!graph) return nullptr;
+    hipGraphExec_t exec = nullptr;
+    record(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+    graphs_.push_back(graph);
+    children_.push_back({exec, graph});
+    return exec;
+  }
+  void launch_graph(void* exec) override {
+    record(hipGraphLaunch(static_cast<hipGraphExec_t>(exec), stream_), "hipGraphLaunch");
+  }
+  void destroy_graph(void* exec) override {
+    if (exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(exec));
+  }
+  void* captured_graph(void* exec) override { return child_of(exec); }
+  void* combine_graphs(void* const* graphs, int n) override {
+    hipGraph_t parent = nullptr;
+    record(hipGraphCreate(&parent, 0), "hipGraphCreate");
+    for (int k = 0; k < n; ++k) {
+      hipGraph_t child = static_cast<hipGraph_t>(graphs[k]);
+      if (!child) { set_err("combine_graphs: missing graph"); return nullptr; }
+      hipGraphNode_t node = nullptr;
+      record(hipGraphAddChildGraphNode(&node, parent, nullptr, 0, child), "hipGraphAddChildGraphNode");
+    }
+    hipGraphExec_t exec = nullptr;
+    record(hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0), "hipGraphInstantiate");
+    graphs_.push_back(parent);
+    return exec;
+  }
+
+
  private:
   struct Timed { hipEvent_t a, b; int ph; };
+  struct Child { void* exec; hipGraph_t graph; };
+  std::vector<hipGraph_t> graphs_;
+  std::vector<Child> children_;
+  bool capturing_ = false;
+  hipGraph_t child_of(void* exec) const {
+    for (const auto& c : children_)
+      if (c.exec == exec) return c.graph;
+    return nullptr;
+  }
   hipStream_t stream_;
   std::string err_;
   unsigned mask_ = 0;
@@ -921,7 +978,7 @@ class HipBackend : public Backend {
     return e;
   }
   void begin() {
-    timing_ = (mask_ >> phase_) & 1u;
+    timing_ = !capturing_ && ((mask_ >> phase_) & 1u);
     if (timing_) {
       cur_a_ = event();
       record(hipEventRecord(cur_a_, stream_), "hipEventRecord");

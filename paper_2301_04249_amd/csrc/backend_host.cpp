@@ -189,11 +189,15 @@ class HostBackend : public Backend {
     e.e_out[1] = ei;
   }
 
-  void cumulant_append(double* c, int64_t k, const double* ep, const double* en, double h) override {
+  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h) override {
     // C + i h (E_k + E_{k+1})
-    const double sr = ep[0] + en[0], si = ep[1] + en[1];
+    const int64_t k = *step;
+    const double sr = e[2 * k] + en[0], si = e[2 * k + 1] + en[1];
     c[2 * (k + 1)] = c[2 * k] - h * si;
     c[2 * (k + 1) + 1] = c[2 * k + 1] + h * sr;
+    e[2 * (k + 1)] = en[0];
+    e[2 * (k + 1) + 1] = en[1];
+    *step = k + 1;
   }
 };
 

@@ -66,6 +66,10 @@ struct Context {
   double* delta = nullptr;
   double* epart = nullptr;
   double* e_hist = nullptr;  // [(max_steps+1)][2]
+  double* e_next = nullptr;  // E(T_{n+1}) of the step in flight
+  int64_t* dstep = nullptr;  // steps taken, on the device (indexes the histories)
+  void* step_graph = nullptr;
+  double graph_dt = 0.0;
   double* c_hist = nullptr;  // [(max_steps+1)][2]
   int64_t nsteps = 0;
   std::vector<double> times;
@@ -169,6 +173,8 @@ struct Context {
     epart = take(be ? be->energy_partials() : 4096);
     e_hist = take(2 * (opt.max_steps + 1));
     c_hist = take(2 * (opt.max_steps + 1));
+    e_next = take(2);
+    dstep = reinterpret_cast<int64_t*>(take(1));
 
     // Cholesky blocks in the extended ordering (host reorder, then copy)
     if (!dry) {
@@ -260,6 +266,7 @@ struct Context {
       be->fill(X, 2 * ns, 0.0);
       be->fill(e_hist, 2, 0.0);
       be->fill(c_hist, 2, 0.0);
+      be->fill(reinterpret_cast<double*>(dstep), 1, 0.0);   // all-zero bits: integer 0
     }
     nsteps = 0;
     times.assign(1, 0.0);
@@ -519,6 +526,39 @@ struct Context {
   // T^(1) = rhs + (i dt/2) R_n; T^(k+1) = rhs + (i dt/2) R(T^(k)).
   int step(double dt) {
     if (nsteps >= opt.max_steps) throw Error(RTEOM_ERR_STATE, "C(t) history is full (max_steps)");
+    const int passes = enqueue_step(dt);
+    ++nsteps;
+    times.push_back(times.back() + dt);
+    return passes;
+  }
+
+  // Fixed-pass steps may be captured once into a graph and replayed: every
+  // argument of a step is either constant or read from device memory.
+  bool graph_mode() const { return opt.reserved0 != 0 && opt.fp_fixed_iters > 0; }
+  void* graph_for(double dt) {
+    if (step_graph && graph_dt == dt) return step_graph;
+    if (step_graph) {
+      be->destroy_graph(step_graph);
+      step_graph = nullptr;
+    }
+    if (!be->begin_capture()) return nullptr;
+    enqueue_step(dt);
+    step_graph = be->end_capture();
+    graph_dt = dt;
+    check();
+    return step_graph;
+  }
+  int step_graphed(double dt) {
+    if (nsteps >= opt.max_steps) throw Error(RTEOM_ERR_STATE, "C(t) history is full (max_steps)");
+    void* g = graph_for(dt);
+    if (!g) return step(dt);
+    be->launch_graph(g);
+    ++nsteps;
+    times.push_back(times.back() + dt);
+    return opt.fp_fixed_iters;
+  }
+
+  int enqueue_step(double dt) {
     UpdateOp u0 = update_op(true);
     u0.h = 0.5 * dt;
     residual(X, R);
@@ -553,10 +593,8 @@ struct Context {
       }
     }
     be->set_phase(kPhaseEnergy);
-    energy(X, e_hist + 2 * (nsteps + 1));
-    be->cumulant_append(c_hist, nsteps, e_hist + 2 * nsteps, e_hist + 2 * (nsteps + 1), 0.5 * dt);
-    ++nsteps;
-    times.push_back(times.back() + dt);
+    energy(X, e_next);
+    be->cumulant_append(c_hist, e_hist, e_next, dstep, 0.5 * dt);
     return passes;
   }
 };
@@ -747,7 +785,7 @@ rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* ite
   if (!(dt > 0.0) || !std::isfinite(dt) || n_steps < 0) { c.err = "dt must be positive and finite, n_steps >= 0"; return RTEOM_ERR_ARG; }
   rteom_status st = guarded(ctx, [&] {
     for (int32_t k = 0; k < n_steps; ++k) {
-      int p = c.step(dt);
+      int p = c.graph_mode() ? c.step_graphed(dt) : c.step(dt);
       if (iters) iters[k] = p;
     }
     c.be->sync();
@@ -828,6 +866,7 @@ rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double
       const double* sc[4] = {c.mo[sp[b][0]], c.mo[sp[b][1]], c.mv[sp[b][0]], c.mv[sp[b][1]]};
       c.eng.scale(c.t2(c.X, b), sc);
     }
+    c.energy(c.X, c.e_hist + 2 * c.nsteps);   // E(T_n) for the next trapezoid
     c.failed = false;
   });
 }
@@ -897,11 +936,76 @@ rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double
   });
 }
 
+struct rteom_batch {
+  std::vector<rteom_ctx*> ctxs;
+  void* exec = nullptr;
+  double dt = 0.0;
+  std::string err;
+};
+
+rteom_status rteom_batch_create(rteom_batch** out, int32_t n, rteom_ctx* const* ctxs) {
+  if (!out || n < 1 || !ctxs) { g_last_error = "bad argument"; return RTEOM_ERR_ARG; }
+  *out = nullptr;
+  for (int32_t k = 0; k < n; ++k) {
+    if (!ctxs[k]) { g_last_error = "NULL context in batch"; return RTEOM_ERR_ARG; }
+    const Context& c = ctxs[k]->c;
+    if (!c.graph_mode()) { g_last_error = "batched contexts need graph mode and fixed passes"; return RTEOM_ERR_STATE; }
+    if (c.failed) { g_last_error = "context in a failed state"; return RTEOM_ERR_STATE; }
+    for (int32_t j = 0; j < k; ++j)
+      if (ctxs[j] == ctxs[k]) { g_last_error = "context listed twice"; return RTEOM_ERR_ARG; }
+  }
+  rteom_batch* b = new rteom_batch();
+  b->ctxs.assign(ctxs, ctxs + n);
+  *out = b;
+  return RTEOM_OK;
+}
+
+rteom_status rteom_batch_step(rteom_batch* b, double dt, int32_t n_steps) {
+  if (!b) { g_last_error = "NULL batch"; return RTEOM_ERR_ARG; }
+  if (!(dt > 0.0) || !std::isfinite(dt) || n_steps < 0) { b->err = "bad dt or n_steps"; g_last_error = b->err; return RTEOM_ERR_ARG; }
+  rteom_ctx* lead = b->ctxs[0];
+  rteom_status st = guarded(lead, [&] {
+    for (rteom_ctx* x : b->ctxs)
+      if (x->c.nsteps + n_steps > x->c.opt.max_steps) throw Error(RTEOM_ERR_STATE, "C(t) history would overflow");
+    if (!b->exec || b->dt != dt) {
+      std::vector<void*> graphs;
+      for (rteom_ctx* x : b->ctxs) {
+        void* e = x->c.graph_for(dt);
+        if (!e) throw Error(RTEOM_ERR_STATE, "graph capture unavailable (null stream?)");
+        graphs.push_back(x->c.be->captured_graph(e));
+        x->c.be->sync();
+      }
+      if (b->exec) lead->c.be->destroy_graph(b->exec);
+      b->exec = lead->c.be->combine_graphs(graphs.data(), (int)graphs.size());
+      if (!b->exec) throw Error(RTEOM_ERR_HIP, "could not build the batch graph");
+      b->dt = dt;
+    }
+    for (int32_t k = 0; k < n_steps; ++k) {
+      lead->c.be->launch_graph(b->exec);
+      for (rteom_ctx* x : b->ctxs) {
+        ++x->c.nsteps;
+        x->c.times.push_back(x->c.times.back() + dt);
+      }
+    }
+    lead->c.be->sync();
+  });
+  if (st != RTEOM_OK) g_last_error = lead->c.err;
+  return st;
+}
+
+rteom_status rteom_batch_free(rteom_batch* b) {
+  if (!b) return RTEOM_OK;
+  if (b->exec && !b->ctxs.empty()) b->ctxs[0]->c.be->destroy_graph(b->exec);
+  delete b;
+  return RTEOM_OK;
+}
+
 rteom_status rteom_free(rteom_ctx* ctx) {
   if (!ctx) return RTEOM_OK;
   Context& c = ctx->c;
   if (c.be) {
     c.be->sync();
+    if (c.step_graph) c.be->destroy_graph(c.step_graph);
     if (c.ws_owned && c.ws) c.be->release(c.ws);
     delete c.be;
   }

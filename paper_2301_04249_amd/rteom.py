@@ -23,7 +23,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
     "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
-    "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_free", "rteom_last_error",
+    "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_batch_create", "rteom_batch_step",
+    "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
 PHASES = ("ladder", "ring", "gemm", "move", "update", "energy")
 
@@ -43,7 +44,7 @@ class Options(ctypes.Structure):
         ("fp_max_iter", ctypes.c_int32),
         ("fp_tol", ctypes.c_double),
         ("dC_include_fT1", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("graph", ctypes.c_int32),
         ("max_steps", ctypes.c_int64),
         ("stream", ctypes.c_void_p),
         ("workspace", ctypes.c_void_p),
@@ -87,6 +88,9 @@ def load(path: str = LIB_PATH):
     lib.rteom_residual_flops.argtypes = [c.c_void_p, _dp]
     lib.rteom_profile.argtypes = [c.c_void_p, c.c_uint32]
     lib.rteom_phase_stats.argtypes = [c.c_void_p, c.c_int32, _dp, _dp, c.POINTER(c.c_int64)]
+    lib.rteom_batch_create.argtypes = [c.POINTER(c.c_void_p), c.c_int32, c.POINTER(c.c_void_p)]
+    lib.rteom_batch_step.argtypes = [c.c_void_p, c.c_double, c.c_int32]
+    lib.rteom_batch_free.argtypes = [c.c_void_p]
     lib.rteom_free.argtypes = [c.c_void_p]
     lib.rteom_last_error.argtypes = [c.c_void_p]
     lib.rteom_last_error.restype = c.c_char_p
@@ -106,7 +110,7 @@ class Propagator:
 
     def __init__(self, eps, chol, n_occ_a, n_occ_b, core_orb=0, core_spin=1, prec="fp64", fp_map=0,
                  fixed_iters=0, max_iter=50, tol=1e-10, include_ft1=True, max_steps=100000,
-                 stream=None, workspace=None, lib_path=LIB_PATH):
+                 stream=None, workspace=None, graph=False, lib_path=LIB_PATH):
         self.lib = load(lib_path)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         chol = np.ascontiguousarray(chol, dtype=np.float64)
@@ -121,6 +125,7 @@ class Propagator:
         opt.fp_tol = float(tol)
         opt.dC_include_fT1 = 1 if include_ft1 else 0
         opt.max_steps = int(max_steps)
+        opt.graph = 1 if graph else 0
         opt.stream = stream
         self._ws = None
         if workspace == "torch":
@@ -133,7 +138,11 @@ class Propagator:
             opt.workspace = self._ws.data_ptr()
             opt.workspace_bytes = int(need.value)
             if stream is None:
-                opt.stream = torch.cuda.current_stream().cuda_stream
+                if graph:   # a stream of its own (at the default priority) so that it can be captured
+                    self._stream = torch.cuda.Stream()
+                    opt.stream = self._stream.cuda_stream
+                else:
+                    opt.stream = torch.cuda.current_stream().cuda_stream
         self.opt = opt
         h = ctypes.c_void_p()
         st = self.lib.rteom_init(ctypes.byref(h), n, n_occ_a, n_occ_b, _ptr(eps), nq, _ptr(chol), core_orb,
@@ -236,6 +245,36 @@ class Propagator:
     def close(self):
         if getattr(self, "h", None):
             self.lib.rteom_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Several propagations advanced together, one graph launch per time step (rteom_batch_*)."""
+
+    def __init__(self, props):
+        self.props = list(props)
+        self.lib = self.props[0].lib
+        arr = (ctypes.c_void_p * len(self.props))(*[p.h.value for p in self.props])
+        h = ctypes.c_void_p()
+        st = self.lib.rteom_batch_create(ctypes.byref(h), len(self.props), arr)
+        if st != 0:
+            raise RteomError(st, self.lib.rteom_last_error(None).decode())
+        self.h = h
+
+    def step(self, dt, n_steps=1):
+        st = self.lib.rteom_batch_step(self.h, float(dt), int(n_steps))
+        if st != 0:
+            raise RteomError(st, self.lib.rteom_last_error(None).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.rteom_batch_free(self.h)
             self.h = None
 
     def __del__(self):

@@ -736,6 +736,7 @@ class HipBackend : public Backend {
     for (auto& e : done_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : pool_) (void)hipEventDestroy(e);
     for (auto& g : graphs_) (void)hipGraphDestroy(g);
+    for (auto& e : graph_timed_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     if (own_stream_) (void)hipStreamDestroy(stream_);
   }
   bool own_stream_ = false;
@@ -756,6 +757,17 @@ class HipBackend : public Backend {
       pool_.push_back(e.b);
     }
     done_.swap(keep);
+    // operations inside captured graphs: their times in the most recent replay
+    for (auto& e : graph_timed_) {
+      if (e.ph != ph) continue;
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+        total += ms;
+        ++n;
+      } else {
+        (void)hipGetLastError();   // graph not replayed yet
+      }
+    }
     if (ops) *ops = n;
     return total;
   }
@@ -968,6 +980,7 @@ class HipBackend : public Backend {
   std::string err_;
   unsigned mask_ = 0;
   std::vector<Timed> done_;
+  std::vector<Timed> graph_timed_;
   std::vector<hipEvent_t> pool_;
   hipEvent_t cur_a_ = nullptr;
   bool timing_ = false;
@@ -978,7 +991,7 @@ class HipBackend : public Backend {
     return e;
   }
   void begin() {
-    timing_ = !capturing_ && ((mask_ >> phase_) & 1u);
+    timing_ = ((mask_ >> phase_) & 1u) != 0;
     if (timing_) {
       cur_a_ = event();
       record(hipEventRecord(cur_a_, stream_), "hipEventRecord");
@@ -988,7 +1001,8 @@ class HipBackend : public Backend {
     if (!timing_) return;
     hipEvent_t b = event();
     record(hipEventRecord(b, stream_), "hipEventRecord");
-    done_.push_back({cur_a_, b, phase_});
+    // recorded during capture: event nodes of the graph, re-recorded by every replay
+    (capturing_ ? graph_timed_ : done_).push_back({cur_a_, b, phase_});
     timing_ = false;
   }
   void set_err(const std::string& m) {

@@ -2,6 +2,7 @@
 #include "engine.h"
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 
 namespace rteom {
@@ -219,9 +220,19 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   bool ctemp = false;
   bool cok = flat(C, cl, Bg, &s0) && flat(C, cl, Mg, &s1) && flat(C, cl, Ng, &s2);
   if (!cok && Bg.empty()) {
+    // Fraction of the 64x64 output tiles that holds useful elements.
+    auto fill = [&](const std::string& m, const std::string& n) {
+      int64_t M = 1, N = 1;
+      for (char c : m) M *= dim_of(c);
+      for (char c : n) N *= dim_of(c);
+      return static_cast<double>(M * N) / static_cast<double>(((M + 63) / 64) * 64 * ((N + 63) / 64) * 64);
+    };
     for (char c : Mg + Ng) {
       std::string m2 = minus(Mg, c), n2 = minus(Ng, c), b2(1, c);
       if (flat(C, cl, b2, &s0) && flat(C, cl, m2, &s1) && flat(C, cl, n2, &s2)) {
+        // promote only if the batched product fills its tiles nearly as well as
+        // one product into a temporary (which costs a permute of the output)
+        if (fill(m2, n2) < 0.6 * fill(Mg, Ng)) continue;
         Bg = b2;
         Mg = m2;
         Ng = n2;
@@ -347,6 +358,12 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   }
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
+#ifdef RTEOM_PLAN_TRACE
+  std::fprintf(stderr, "PLAN %-22s M=%lld N=%lld K=%lld batch=%lld split=%d A%s%s B%s%s ctemp=%d flops=%.3g\n",
+               spec_str, (long long)op.M, (long long)op.N, (long long)op.K, (long long)op.batch, op.splitk,
+               op.a_im ? "c" : "r", op.a_sk == 1 ? "k" : "m", op.b_im ? "c" : "r", op.b_sk == 1 ? "k" : "n",
+               (int)ctemp, f);
+#endif
   flops += f;
   phase_flops[phase] += f;
   if (op.M > 0 && op.N > 0 && op.batch > 0 && !dry) {

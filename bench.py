@@ -21,22 +21,37 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from synthetic import FORMALDEHYDE, TINY, draw_system  # noqa: E402
+from synthetic import ESCA_PAPER, FORMALDEHYDE, TINY, draw_system  # noqa: E402
+
+# Ladder kernel per precision (the contraction's MFMA instruction family)
+KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float>", "bf16x3": "gemm_bf16x3"}
+
+# HBM bytes per ladder launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
+# scaled by the same counters read on a plain device copy of known size; the
+# summaries (with the commands) are under profiles/.  Only workloads whose
+# ladder kernel has been counted since its last change are listed.
+TRAFFIC = {}
 
 # MI355X published peaks (dense)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
 WORKLOADS = {
-    "formaldehyde": dict(shape=FORMALDEHYDE, cfg=1, dt=0.025, passes=3,
+    "formaldehyde": dict(shape=FORMALDEHYDE, cfg=1, dt=0.025, passes=3, steps=4,
                          desc="formaldehyde-shaped core hole: o=8, v=110 per spin, Q=600, beta hole, dt=0.025 au"),
-    "tiny": dict(shape=TINY, cfg=0, dt=0.025, passes=3,
+    "tiny": dict(shape=TINY, cfg=0, dt=0.025, passes=3, steps=4,
                  desc="tiny: o=4, v=16 per spin, Q=48, beta hole, dt=0.025 au"),
+    # the paper's ESCA run: 71 occupied / 649 virtual spin-orbitals in total
+    # (an 83 GiB (ae|bf) block: one residual is far beyond the oracle's reach on
+    # the host, so its CPU baseline is timed on the formaldehyde-shaped system)
+    "esca": dict(shape=ESCA_PAPER, cfg=3, dt=0.01, passes=2, steps=2, large=True, cpu_sample="formaldehyde",
+                 desc="ESCA-shaped core hole as in the paper's run: o=36, v=324 per spin (71/649 spin-orbitals "
+                      "with the beta hole), Q=2000, dt=0.01 au"),
 }
 
 
-def cpu_baseline(work, eps, chol, flops_per_residual):
-    """The oracle as it stands: one residual evaluation of the same workload on the host."""
+def cpu_baseline(name, eps, chol, flops_per_residual):
+    """The oracle as it stands: one residual evaluation of workload ``name`` on the host."""
     sys.path.insert(0, os.path.join(ROOT, "tests"))
     import blocks
     from oracle import ccsd, reference
@@ -45,7 +60,7 @@ def cpu_baseline(work, eps, chol, flops_per_residual):
         threads = max(int(x.get("num_threads", 1)) for x in threadpoolctl.threadpool_info()) or 1
     except Exception:  # pragma: no cover
         threads = os.cpu_count() or 1
-    shape = work["shape"]
+    shape = WORKLOADS[name]["shape"]
     sysm = reference.n_minus_one_reference(eps, chol, shape.o, shape.o, 0, 1, lean=True)
     t1, t2 = blocks.random_spin_orbital_amplitudes(sysm, 17, scale=1e-3)
     ccsd._blocks(sysm)                    # integral blocks are built once per propagation
@@ -53,17 +68,17 @@ def cpu_baseline(work, eps, chol, flops_per_residual):
     ccsd.residual(sysm, t1, t2)
     dt = time.perf_counter() - t0
     return {"value": flops_per_residual / dt / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
-            "sample": f"one residual evaluation R(T) of the {shape.o}/{shape.v}/Q={shape.nchol} workload at seeded "
-                      f"amplitudes (spin-orbital oracle, lean integral blocks): {dt:.2f} s; rate = the GPU path's "
-                      f"flop count of one residual / that time"}
+            "sample": f"one residual evaluation R(T) of the {name} workload (o={shape.o}, v={shape.v} per spin, "
+                      f"Q={shape.nchol}) at seeded amplitudes (spin-orbital oracle, lean integral blocks): "
+                      f"{dt:.2f} s; rate = the GPU path's flop count of that residual / that time"}
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=4)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: per workload)")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="formaldehyde", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="esca", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -89,6 +104,8 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     work = WORKLOADS[args.workload]
+    if args.steps is None:
+        args.steps = work["steps"]
     shape = work["shape"]
     eps, chol = draw_system(shape, cfg=work["cfg"])
     print(f"[bench] workload {args.workload}: {work['desc']}", file=sys.stderr, flush=True)
@@ -97,12 +114,13 @@ def main(argv=None):
     def run(graph):
         P = rteom.Propagator(eps, chol, shape.o, shape.o, 0, 1, prec=args.prec, fixed_iters=work["passes"],
                              workspace="torch", max_steps=args.steps + args.warmup + 4, graph=graph)
-        # HIP events around the dominant kernel only; in graph mode they are event
-        # nodes of the captured step, re-recorded by every replay
-        P.profile(("ladder",))
+        if not graph:
+            P.profile(("ladder",))        # HIP events around the dominant kernel only
+        print(f"[bench] {'graph' if graph else 'direct'} launches: context ready", file=sys.stderr, flush=True)
         if args.warmup:
             P.step(dt, args.warmup)
         torch.cuda.synchronize()
+        print(f"[bench] warmup done ({args.warmup} steps)", file=sys.stderr, flush=True)
         for ph in rteom.PHASES:
             P.phase_stats(ph)             # clear
         torch.cuda.synchronize()
@@ -110,17 +128,31 @@ def main(argv=None):
         iters = P.step(dt, args.steps)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
+        print(f"[bench] timed {args.steps} steps: {(t1 - t0) * 1e3 / args.steps:.2f} ms/step", file=sys.stderr,
+              flush=True)
         stats = P.phase_stats("ladder")
         return P, iters, t0, t1, stats
 
-    mode = "graph"
-    try:
-        P, iters, t0, t1, (lad_ms, lad_ops, lad_flops) = run(True)
-    except rteom.RteomError as exc:    # graph capture unavailable: launch operations directly
-        print(f"[bench] graph mode failed ({exc}); direct launches", file=sys.stderr, flush=True)
-        mode = "direct"
+    # Timed region 1 gives the value.  Small workloads replay each step as a
+    # hipGraph (launch overhead matters there); large ones launch directly, with
+    # HIP events around every ladder launch in the same region.
+    mode = "direct" if work.get("large") else "graph"
+    if mode == "graph":
+        try:
+            P, iters, t0, t1, _ = run(True)
+        except rteom.RteomError as exc:    # graph capture unavailable: launch operations directly
+            print(f"[bench] graph mode failed ({exc}); direct launches", file=sys.stderr, flush=True)
+            mode = "direct"
+    ms_direct = None
+    if mode == "graph":
+        # Timed region 2 (roofline only): the same steps with direct launches and
+        # HIP events around every ladder launch; events cannot time kernels inside
+        # a replayed graph.
+        P2, _, u0, u1, (lad_ms, lad_ops, lad_flops) = run(False)
+        ms_direct = (u1 - u0) * 1e3 / args.steps
+        P2.close()
+    else:
         P, iters, t0, t1, (lad_ms, lad_ops, lad_flops) = run(False)
-    P.profile(())
     flops_res = P.residual_flops()
     n_res = int(np.sum(iters))
     ms_per_step = (t1 - t0) * 1e3 / args.steps
@@ -130,6 +162,15 @@ def main(argv=None):
         print("bench.py: non-finite C(t)", file=sys.stderr)
         return 3
     achieved = lad_flops * lad_ops / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
+    avg_ms = lad_ms / lad_ops if lad_ops else None
+    traffic = TRAFFIC.get((args.workload, args.prec))
+    peak = PEAK_TFLOPS[args.prec]
+    launch = {"graph": "graph (each time step captured once as a hipGraph and replayed)",
+              "direct": "direct (every operation launched on one HIP stream)"}[mode]
+    config = {"workload": work["desc"], "passes_per_step": work["passes"], "residuals_timed": n_res,
+              "launch": launch, "flops_per_residual": flops_res, "s_per_residual": (t1 - t0) / n_res}
+    if ms_direct is not None:
+        config["ms_per_step_direct_launch"] = round(ms_direct, 4)
     out = {
         "metric": "residual TFLOP/s (time step of the RT-EOM-CCSD hot path)",
         "value": round(value, 4),
@@ -141,22 +182,32 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 update", "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}[args.prec],
+        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 update",
+                  "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}[args.prec],
         "data": "synthetic (seeded eps and Cholesky vectors of the stated shape)",
-        "config": {"workload": work["desc"], "passes_per_step": work["passes"], "residuals_timed": n_res,
-                   "launch": mode + (" (each time step captured once as a hipGraph and replayed)" if mode == "graph" else ""),
-                   "flops_per_residual": flops_res, "s_per_residual": (t1 - t0) / n_res},
-        "roofline": {"kernel": "gemm_f64 particle-particle ladder (3 spin blocks in one launch)",
-                     "bound": "mfma", "achieved": round(achieved, 4), "peak": PEAK_TFLOPS[args.prec],
-                     "unit": "TFLOP/s", "frac": round(achieved / PEAK_TFLOPS[args.prec], 5), "traffic": None,
+        "config": config,
+        "roofline": {"kernel": KERNEL_NAME[args.prec] + " particle-particle ladder (3 spin blocks in one launch)",
+                     "bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 5),
+                     "traffic": traffic,
                      "launches": lad_ops, "flops_per_launch": lad_flops,
-                     "timing": "HIP events around the ladder launches" + (
-                         " (event nodes of the step graph: the launches of the last timed step)" if mode == "graph"
-                         else " in the timed region"),
-                     "avg_launch_ms": (lad_ms / lad_ops) if lad_ops else None},
+                     "avg_launch_ms": round(avg_ms, 5) if avg_ms else None,
+                     "timing": "HIP events on the engine stream around each ladder launch, " + (
+                         "in a second timed region of the same steps with direct launches" if mode == "graph"
+                         else "in the timed region")},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(work, eps, chol, flops_res)
+        name = work.get("cpu_sample", args.workload)
+        if name != args.workload:
+            P.close()
+            del P
+            sw = WORKLOADS[name]
+            eps, chol = draw_system(sw["shape"], cfg=sw["cfg"])
+            Q = rteom.Propagator(eps, chol, sw["shape"].o, sw["shape"].o, 0, 1, prec=args.prec,
+                                 fixed_iters=sw["passes"], workspace="torch", max_steps=2)
+            flops_res = Q.residual_flops()
+            Q.close()
+        out["cpu_baseline"] = cpu_baseline(name, eps, chol, flops_res)
     print(json.dumps(out), flush=True)
     return 0
 

@@ -359,10 +359,10 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
 #ifdef RTEOM_PLAN_TRACE
-  std::fprintf(stderr, "PLAN %-22s M=%lld N=%lld K=%lld batch=%lld split=%d A%s%s B%s%s ctemp=%d flops=%.3g\n",
+  std::fprintf(stderr, "PLAN %-22s M=%lld N=%lld K=%lld batch=%lld split=%d A%s%s B%s%s ctemp=%d flops=%.3g arena=%.2fGiB\n",
                spec_str, (long long)op.M, (long long)op.N, (long long)op.K, (long long)op.batch, op.splitk,
                op.a_im ? "c" : "r", op.a_sk == 1 ? "k" : "m", op.b_im ? "c" : "r", op.b_sk == 1 ? "k" : "n",
-               (int)ctemp, f);
+               (int)ctemp, f, scratch->mark() / 1073741824.0);
 #endif
   flops += f;
   phase_flops[phase] += f;

@@ -20,6 +20,7 @@
 // * Step.  Implicit trapezoid (Eq. trapzrule) with fixed-point passes; three
 //   amplitude-sized buffers (iterate X, rhs, residual R) as in Table 2's three
 //   timeline tensors.  C(t) accumulates i E(T) with the same trapezoid weights.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <memory>
@@ -34,6 +35,9 @@
 namespace rteom {
 
 Backend* make_host_backend();
+
+// Largest GEMM-order temporary of the integral-block build (2 GiB of doubles).
+constexpr int64_t kSlabDoubles = int64_t(1) << 28;
 
 struct Context {
   rteom_options opt{};
@@ -257,10 +261,22 @@ struct Context {
     // Resident integral blocks (spin free)
     eng.contract("Qme,Qnf->menf", Lv(Lov, no, nv), Lv(Lov, no, nv),
                  make_view(Jov, nullptr, {no, nv, no, nv}), 1.0, 0);
-    eng.contract("Qae,Qbf->efab", Lv(Lvv, nv, nv), Lv(Lvv, nv, nv),
-                 make_view(Vlad, nullptr, {nv, nv, nv, nv}), 1.0, 0);
-    eng.contract("Qme,Qbf->efmb", Lv(Lov, no, nv), Lv(Lvv, nv, nv),
-                 make_view(B1, nullptr, {nv, nv, no, nv}), 1.0, 0);
+    // (ae|bf) and (me|bf) are built in slabs of e: the product lands in a temporary
+    // in GEMM order before it is permuted into place, and a slab bounds that
+    // temporary to kSlabDoubles instead of a second copy of the whole block.
+    {
+      const int64_t per_e = std::max<int64_t>(1, (int64_t)nv * nv * nv);
+      const int64_t ce = std::max<int64_t>(1, std::min<int64_t>(nv, kSlabDoubles / per_e));
+      View Vv = make_view(Vlad, nullptr, {nv, nv, nv, nv});
+      View Bv = make_view(B1, nullptr, {nv, nv, no, nv});
+      for (int64_t e0 = 0; e0 < nv; e0 += ce) {
+        const int64_t n = std::min<int64_t>(ce, nv - e0);
+        View Le = block(Lv(Lvv, nv, nv), {0, 0, e0}, {Q, nv, n});
+        View Lm = block(Lv(Lov, no, nv), {0, 0, e0}, {Q, no, n});
+        eng.contract("Qae,Qbf->efab", Le, Lv(Lvv, nv, nv), block(Vv, {e0, 0, 0, 0}, {n, nv, nv, nv}), 1.0, 0);
+        eng.contract("Qme,Qbf->efmb", Lm, Lv(Lvv, nv, nv), block(Bv, {e0, 0, 0, 0}, {n, nv, no, nv}), 1.0, 0);
+      }
+    }
     // T(0) = 0, C(0) = 0
     if (!dry) {
       be->fill(X, 2 * ns, 0.0);

@@ -47,6 +47,9 @@ class Shape:
 TINY = Shape(o=4, v=16, nchol=48)
 FORMALDEHYDE = Shape(o=8, v=110, nchol=600)
 ESCA = Shape(o=71, v=649, nchol=2000)
+# The paper's ESCA spectra run has 71 occupied and 649 virtual spin-orbitals in
+# total (abstract): 36 + 35 occupied, 324 + 325 virtual with the beta hole.
+ESCA_PAPER = Shape(o=36, v=324, nchol=2000)
 ZN_PORPHYRIN = Shape(o=95, v=560, nchol=3000)
 
 

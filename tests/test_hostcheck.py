@@ -80,3 +80,12 @@ def test_input_validation():
     with pytest.raises(rteom.RteomError) as ex:
         P.step(-0.1, 1)
     assert ex.value.status == 1
+
+
+def test_embedded_system_property():
+    """The size-extensivity check used at the ESCA-shaped size, here on the host engine
+    (o=7, v=26 per spin with a 3/5/Q=12 part holding the core hole)."""
+    import embedding
+    emb = embedding.build(Shape(7, 26, 40), 5, 3, 5, 12)
+    P = rteom.Propagator(emb["eps"], emb["chol"], 7, 7, 0, 1, lib_path=LIB)
+    embedding.check(P, emb, "fp64", 1e-12)

@@ -299,3 +299,65 @@ def test_lean_mode_matches_dense():
     b1, b2 = ccsd.residual(lean, t1, t2)
     assert np.abs(a1 - b1).max() < 1e-13 and np.abs(a2 - b2).max() < 1e-13
     assert abs(ccsd.energy(dense, t1, t2) - ccsd.energy(lean, t1, t2)) < 1e-14
+
+
+def test_size_extensivity_of_residual_and_energy():
+    """CCSD is size-extensive: for two parts with no integral between them (block-diagonal
+    Cholesky vectors on disjoint Q ranges) and amplitudes inside each part, the residual on
+    each part is that part's own residual, every element joining them vanishes, and the
+    energy is the sum.  Pins the connectedness of every term of the oracle's equations."""
+    o, v, q, qa = 5, 9, 24, 10
+    n = o + v
+    eps, chol = draw_system(Shape(o, v, q), cfg=41, chol_scale=2.0)
+    in_a = np.zeros(n, dtype=bool)
+    in_a[:2] = True                 # part A: occupied 0, 1 (core orbital 0) and 3 virtuals
+    in_a[o:o + 3] = True
+    chol[:qa] *= in_a[:, None] & in_a[None, :]
+    chol[qa:] *= ~in_a[:, None] & ~in_a[None, :]
+    big = reference.n_minus_one_reference(eps, chol, o, o, 0, 1)
+
+    def part(mask, qs, hole):
+        sel = np.flatnonzero(mask)
+        e, c = eps[sel], np.ascontiguousarray(chol[qs][:, sel][:, :, sel])
+        m, no_p = len(sel), int(np.sum(sel < o))
+        if hole:
+            sub = reference.n_minus_one_reference(e, c, no_p, no_p, 0, 1)
+        else:                       # closed-shell N-electron part: Fock diagonal eps
+            occ = np.array([p + m * s for s in (0, 1) for p in range(no_p)])
+            vir = np.array(sorted(set(range(2 * m)) - set(occ.tolist())))
+            sub = reference.SpinOrbitalSystem(
+                n=m, eps=e, chol=c, occ=occ, vir=vir, core=-1, fock=np.diag(np.concatenate([e, e])),
+                g=reference.antisymmetrized_spin_orbital(reference.coulomb_from_cholesky(c)))
+        # spin-orbital of the big system -> spin-orbital of the part
+        so = {int(p) + s * n: int(k) + s * m for s in (0, 1) for k, p in enumerate(sel)}
+        oc = [k for k, x in enumerate(big.occ) if int(x) in so]
+        vi = [k for k, x in enumerate(big.vir) if int(x) in so]
+        pos_o = {int(x): k for k, x in enumerate(sub.occ)}
+        pos_v = {int(x): k for k, x in enumerate(sub.vir)}
+        return (sub, np.array(oc), np.array(vi), np.array([pos_o[so[int(big.occ[k])]] for k in oc]),
+                np.array([pos_v[so[int(big.vir[k])]] for k in vi]))
+
+    parts = [part(in_a, slice(None, qa), True), part(~in_a, slice(qa, None), False)]
+    t1 = np.zeros((big.no, big.nv), dtype=complex)
+    t2 = np.zeros((big.no, big.no, big.nv, big.nv), dtype=complex)
+    amps = []
+    for k, (sub, oc, vi, so_, sv_) in enumerate(parts):
+        st1, st2 = _random_amplitudes(sub, 100 + k)
+        assert len(so_) == sub.no and len(sv_) == sub.nv
+        t1[np.ix_(oc, vi)] = st1[np.ix_(so_, sv_)]
+        t2[np.ix_(oc, oc, vi, vi)] = st2[np.ix_(so_, so_, sv_, sv_)]
+        amps.append((st1, st2))
+    r1, r2 = ccsd.residual(big, t1, t2)
+    covered1 = np.zeros(r1.shape, dtype=bool)
+    covered2 = np.zeros(r2.shape, dtype=bool)
+    e_sum = 0.0
+    for (sub, oc, vi, so_, sv_), (st1, st2) in zip(parts, amps):
+        s1, s2 = ccsd.residual(sub, st1, st2)
+        assert np.abs(r1[np.ix_(oc, vi)] - s1[np.ix_(so_, sv_)]).max() < 1e-12
+        assert np.abs(r2[np.ix_(oc, oc, vi, vi)] - s2[np.ix_(so_, so_, sv_, sv_)]).max() < 1e-12
+        covered1[np.ix_(oc, vi)] = True
+        covered2[np.ix_(oc, oc, vi, vi)] = True
+        e_sum += ccsd.energy(sub, st1, st2)
+    assert np.abs(r1[~covered1]).max() < 1e-13
+    assert np.abs(r2[~covered2]).max() < 1e-13
+    assert abs(ccsd.energy(big, t1, t2) - e_sum) < 1e-12

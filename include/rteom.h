@@ -135,7 +135,8 @@ rteom_status rteom_residual(rteom_ctx* ctx, double* r1_out, double* r2_out);
 rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
 
 /* Floating-point operations of one residual evaluation as this implementation performs
-   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex). */
+   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex).
+   Known from rteom_init on (the contraction plan fixes it). */
 rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
 
 /* Device timing by phase of the hot path: 0 particle-ladder GEMM, 1 o^3 v^3 ring / W / Z

@@ -49,6 +49,27 @@ struct GemmArgs {
   int m_fast;                 // logical tile order: row tiles fastest (B is the larger operand)
 };
 
+// Output tile of work-group `bid`.  Work-groups are dispatched round-robin over
+// the 8 XCDs; each XCD gets a contiguous range of logical tiles, so the ~64
+// work-groups resident on one XCD hold consecutive logical tiles.  Logical
+// tiles run in bands of kGroup tiles along one dimension (M when m_fast), the
+// other dimension outermost within a band: the resident work-groups then cover
+// about kGroup x kGroup tiles and read kGroup panels of each operand, each
+// panel shared through that XCD's L2 by kGroup work-groups.
+constexpr int64_t kGroup = 8;
+__device__ inline void tile_coords(const GemmArgs& g, int64_t bid, int64_t& tm, int64_t& tn) {
+  const int64_t nt = g.tiles_m * g.tiles_n;
+  const int64_t q = nt / 8, r = nt % 8, xcd = bid % 8, slot = bid / 8;
+  const int64_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
+  const int64_t tf = g.m_fast ? g.tiles_m : g.tiles_n;     // banded dimension
+  const int64_t ts = g.m_fast ? g.tiles_n : g.tiles_m;
+  const int64_t band = logical / (kGroup * ts), within = logical % (kGroup * ts);
+  const int64_t width = min(kGroup, tf - band * kGroup);
+  const int64_t f = band * kGroup + within % width, o = within / width;
+  if (g.m_fast) { tm = f; tn = o; }
+  else          { tn = f; tm = o; }
+}
+
 // Operand tiles are staged k-major in LDS ([BK][BM] for A, [BK][BN] for B) so
 // that the MFMA fragment reads (row = lane % 16, k = lane / 16) are unit stride
 // across lanes.  The next K tile is loaded into registers while the current one
@@ -89,17 +110,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  // Work-groups are dispatched round-robin over the 8 XCDs.  Give each XCD a
-  // contiguous range of logical tiles, ordered so that neighbours share the
-  // larger operand's tile and reuse it from that XCD's L2.
   int64_t tm, tn;
-  {
-    const int64_t nt = g.tiles_m * g.tiles_n, bid = blockIdx.x;
-    const int64_t q = nt / 8, r = nt % 8, xcd = bid % 8, slot = bid / 8;
-    const int64_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    if (g.m_fast) { tm = logical % g.tiles_m; tn = logical / g.tiles_m; }
-    else          { tn = logical % g.tiles_n; tm = logical / g.tiles_n; }
-  }
+  tile_coords(g, blockIdx.x, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   // staging coordinates of this thread (4 elements per operand plane)
   int a_k[4], a_m[4], b_k[4], b_n[4];
@@ -284,13 +296,7 @@ __global__ __launch_bounds__(kThreads) void gemm_bf16x3(GemmArgs g) {
   const int lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
-  {
-    const int64_t nt = g.tiles_m * g.tiles_n, bid = blockIdx.x;
-    const int64_t q = nt / 8, r = nt % 8, xcd = bid % 8, slot = bid / 8;
-    const int64_t logical = xcd < r ? xcd * (q + 1) + slot : r * (q + 1) + (xcd - r) * q + slot;
-    if (g.m_fast) { tm = logical % g.tiles_m; tn = logical / g.tiles_m; }
-    else          { tn = logical % g.tiles_n; tm = logical / g.tiles_n; }
-  }
+  tile_coords(g, blockIdx.x, tm, tn);
   const int64_t m0 = tm * BM, n0 = tn * BN;
   int a_k[8], a_m[8], b_k[8], b_n[8];
 #pragma unroll

@@ -692,6 +692,29 @@ void rteom_default_options(rteom_options* o) {
   o->max_steps = 100000;
 }
 
+// Plan init + one residual without touching a device: the workspace peak and the
+// residual's flop counts (total and by phase).
+static rteom_status dry_plan(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol,
+                             int32_t core_orb, int32_t core_spin, const rteom_options& o, size_t* bytes,
+                             double* flops, double* phase_flops) {
+  std::unique_ptr<rteom_ctx> ctx(new rteom_ctx());
+  Context& c = ctx->c;
+  c.dry = true;
+  c.opt = o;
+  c.n = n_orb; c.nq = n_chol; c.na = n_occ_a; c.nb = n_occ_b; c.core_orb = core_orb; c.core_spin = core_spin;
+  c.arena.init(nullptr, ~static_cast<size_t>(0) >> 2);
+  const rteom_status st = guarded(ctx.get(), [&] {
+    c.init(nullptr, nullptr);
+    c.residual(c.X, c.R);
+  });
+  if (st != RTEOM_OK) { g_last_error = c.err; return st; }
+  *bytes = c.arena.peak() + (1 << 20);
+  if (flops) *flops = c.res_flops;
+  if (phase_flops)
+    for (int k = 0; k < rteom::kNumPhases; ++k) phase_flops[k] = c.res_phase_flops[k];
+  return RTEOM_OK;
+}
+
 rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol,
                                    int32_t core_orb, int32_t core_spin, const rteom_options* opt,
                                    size_t* bytes) {
@@ -703,19 +726,7 @@ rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ
   rteom_default_options(&o);
   if (opt) o = *opt;
   if (!valid_options(&o, &m)) { g_last_error = m; return RTEOM_ERR_ARG; }
-  std::unique_ptr<rteom_ctx> ctx(new rteom_ctx());
-  Context& c = ctx->c;
-  c.dry = true;
-  c.opt = o;
-  c.n = n_orb; c.nq = n_chol; c.na = n_occ_a; c.nb = n_occ_b; c.core_orb = core_orb; c.core_spin = core_spin;
-  c.arena.init(nullptr, ~static_cast<size_t>(0) >> 2);
-  st = guarded(ctx.get(), [&] {
-    c.init(nullptr, nullptr);
-    c.residual(c.X, c.R);
-  });
-  if (st != RTEOM_OK) { g_last_error = c.err; return st; }
-  *bytes = c.arena.peak() + (1 << 20);
-  return RTEOM_OK;
+  return dry_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, bytes, nullptr, nullptr);
 }
 
 rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
@@ -749,11 +760,14 @@ rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t
         }
       }
   size_t need = 0;
-  st = rteom_workspace_query(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, &o, &need);
+  double plan_flops = 0.0, plan_phase_flops[rteom::kNumPhases] = {0};
+  st = dry_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, &need, &plan_flops, plan_phase_flops);
   if (st != RTEOM_OK) return st;
   std::unique_ptr<rteom_ctx> ctx(new rteom_ctx());
   Context& c = ctx->c;
   c.opt = o;
+  c.res_flops = plan_flops;       // known from the plan before the first evaluation
+  for (int k = 0; k < rteom::kNumPhases; ++k) c.res_phase_flops[k] = plan_phase_flops[k];
   c.n = n_orb; c.nq = n_chol; c.na = n_occ_a; c.nb = n_occ_b; c.core_orb = core_orb; c.core_spin = core_spin;
   std::string berr;
 #ifdef RTEOM_HOST_BACKEND

@@ -89,3 +89,14 @@ def test_embedded_system_property():
     emb = embedding.build(Shape(7, 26, 40), 5, 3, 5, 12)
     P = rteom.Propagator(emb["eps"], emb["chol"], 7, 7, 0, 1, lib_path=LIB)
     embedding.check(P, emb, "fp64", 1e-12)
+
+
+def test_residual_flops_known_at_init():
+    """The flop count of one residual comes from the contraction plan: available right after
+    init and unchanged by evaluating a residual."""
+    eps, chol = draw_system(Shape(3, 5, 10), cfg=3)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB)
+    f0 = P.residual_flops()
+    assert f0 > 0
+    P.residual(False)
+    assert P.residual_flops() == f0

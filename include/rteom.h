@@ -76,16 +76,21 @@ typedef struct {
   int32_t fp_max_iter;     /* pass limit when tolerance driven */
   double fp_tol;           /* max |T^(k+1) - T^(k)| over all amplitudes that ends the passes */
   int32_t dC_include_fT1;  /* 1: dC/dt includes sum f_ia t_ia (Eq. cum_gf3); 0: Eq. dcdt as printed */
-  int32_t reserved0;       /* graph mode: 1 = with fp_fixed_iters > 0 and a non-null stream, each
-                              time step is captured once as a hipGraph and replayed */
+  int32_t graph;           /* 1: with fp_fixed_iters > 0 and a non-null stream, each time step
+                              is captured once as a hipGraph and replayed */
   int64_t max_steps;       /* capacity of the device C(t) history (time steps) */
   void* stream;            /* hipStream_t borrowed from the caller; NULL = null stream */
   void* workspace;         /* caller-owned device memory, or NULL (library allocates) */
   size_t workspace_bytes;  /* size of workspace */
+  int32_t tune;            /* 1: the first time a GEMM shape is met outside graph capture, each
+                              candidate tile shape is timed on it and the fastest is kept for
+                              the context (results are bit-identical for every tile shape);
+                              0: tile shape from a work-per-byte rule */
+  int32_t reserved1;       /* must be 0 */
 } rteom_options;
 
 /* Fill *opt with defaults: FP64, plain map, tolerance 1e-10, 50 passes,
-   dC_include_fT1 = 1, max_steps = 100000, null stream, no workspace. */
+   dC_include_fT1 = 1, no graph, max_steps = 100000, null stream, no workspace, tune = 1. */
 void rteom_default_options(rteom_options* opt);
 
 /* Device bytes rteom_init needs for these sizes and options (no GPU work). */

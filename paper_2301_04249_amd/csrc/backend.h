@@ -109,6 +109,12 @@ class Backend {
   virtual ~Backend() {}
   virtual void set_phase(int ph) { phase_ = ph; }
   virtual void set_profile(unsigned mask) { (void)mask; }
+  // GEMM tile shape: 1 = time the candidates the first time a shape is met
+  // (outside capture) and keep the fastest, 0 = work-per-byte rule.
+  virtual void set_tuning(int on) { (void)on; }
+  // Test hook: force one tile shape (0: 64x64, 1: 64x128, 2: 128x64,
+  // 3: 128x128) where the operand types allow it; -1 = automatic.
+  virtual void force_tile(int v) { (void)v; }
   // total milliseconds and operation count of the profiled phase since the last call
   virtual double phase_ms(int ph, int64_t* ops) { (void)ph; if (ops) *ops = 0; return 0.0; }
  protected:

@@ -2,8 +2,8 @@
 //
 //  gemm_mfma  complex/real GEMM on the matrix cores in float64
 //             (v_mfma_f64_16x16x4f64) or float32 (v_mfma_f32_16x16x4f32),
-//             64x64 output tile per 256-thread work-group, operands staged
-//             through LDS.  Complex operands are planar; a complex x complex
+//             64x64, 64x128, 128x64 or 128x128 output tile per 256-thread
+//             work-group, operands staged through LDS.  Complex operands are planar; a complex x complex
 //             product is four real MFMA products per fragment, complex x real
 //             two.  Split-K and an XCD-aware tile order fill the 256 CUs.
 //  gemm_bf16x3  the same product with bf16 hi/lo operands, three
@@ -16,9 +16,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -92,14 +94,20 @@ template <> struct Mfma<float> {
   static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-template <typename T, bool AC, bool BC, bool AKC, bool BKC>
+// Work-group tile (32*WM) x (32*WN): four waves in a 2 x 2 arrangement, each
+// holding WM x WN accumulator blocks of 16 x 16.  Wider tiles stage fewer
+// operand bytes per MFMA; the complex x complex product already has four MFMAs
+// per staged fragment pair and keeps 64 x 64.
+template <typename T, bool AC, bool BC, bool AKC, bool BKC, int WM, int WN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_mfma(GemmArgs g) {
   typedef typename Mfma<T>::acc_t acc_t;
+  constexpr int TM = 32 * WM, TN = 32 * WN;
+  constexpr int NA = TM * BK / kThreads, NB = TN * BK / kThreads;   // staged elements per thread and plane
   // LDS tiles: a k-contiguous operand is kept [row][BK + 1] (odd stride: the
   // coalesced writes and the fragment reads are both free of bank conflicts),
   // otherwise [k][row + 16] (the two 16-lane halves of a read hit disjoint banks).
-  constexpr int AR = AKC ? BM : BK, AC_ = AKC ? BK + 1 : BM + 16;
-  constexpr int BR = BKC ? BN : BK, BC_ = BKC ? BK + 1 : BN + 16;
+  constexpr int AR = AKC ? TM : BK, AC_ = AKC ? BK + 1 : TM + 16;
+  constexpr int BR = BKC ? TN : BK, BC_ = BKC ? BK + 1 : TN + 16;
   __shared__ T sa_r[2][AR][AC_];
   __shared__ T sa_i[AC ? 2 : 1][AC ? AR : 1][AC_];
   __shared__ T sb_r[2][BR][BC_];
@@ -112,16 +120,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
   const int wm = wave >> 1, wn = wave & 1;
   int64_t tm, tn;
   tile_coords(g, blockIdx.x, tm, tn);
-  const int64_t m0 = tm * BM, n0 = tn * BN;
-  // staging coordinates of this thread (4 elements per operand plane)
-  int a_k[4], a_m[4], b_k[4], b_n[4];
-#pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    if (AKC) { a_k[r] = tid & 15; a_m[r] = (tid >> 4) + 16 * r; }
-    else     { a_m[r] = tid & 63; a_k[r] = (tid >> 6) + 4 * r; }
-    if (BKC) { b_k[r] = tid & 15; b_n[r] = (tid >> 4) + 16 * r; }
-    else     { b_n[r] = tid & 63; b_k[r] = (tid >> 6) + 4 * r; }
-  }
+  const int64_t m0 = tm * TM, n0 = tn * TN;
+  // Staging: element r of this thread sits at (row, k) = (am0 + r * AMS, ak0 + r * AKS)
+  // of the A tile (likewise for B), so one base offset per operand and strides
+  // that are the same for every thread address all of them.
+  constexpr int AMS = AKC ? 16 : 0, AKS = AKC ? 0 : kThreads / TM;
+  constexpr int BNS = BKC ? 16 : 0, BKS = BKC ? 0 : kThreads / TN;
+  const int am0 = AKC ? (tid >> 4) : (tid % TM), ak0 = AKC ? (tid & 15) : (tid / TM);
+  const int bn0 = BKC ? (tid >> 4) : (tid % TN), bk0 = BKC ? (tid & 15) : (tid / TN);
+  const int lda0 = A_at(ak0, am0), ldb0 = B_at(bk0, bn0);
+  const int ldas = A_at(AKS, AMS) - A_at(0, 0), ldbs = B_at(BKS, BNS) - B_at(0, 0);
 
   int64_t kbeg = 0, kend = g.K, b0 = blockIdx.y, bstep = gridDim.y;
   if (g.splitk > 1) {
@@ -130,36 +138,41 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     b0 = 0;
     bstep = 1;
   }
+  const int64_t a_rs = AMS * g.asm_ + AKS * g.ask, b_rs = BKS * g.bsk + BNS * g.bsn;
+  const int64_t a_off = (m0 + am0) * g.asm_ + ak0 * g.ask, b_off = (n0 + bn0) * g.bsn + bk0 * g.bsk;
+  const int64_t a_mrem = g.M - m0 - am0, b_nrem = g.N - n0 - bn0;   // rows / columns left
   for (int64_t b = b0; b < g.batch; b += bstep) {
     const double* Ar = g.ar + b * g.asb;
     const double* Ai = AC ? g.ai + b * g.asb : nullptr;
     const double* Br = g.br + b * g.bsb;
     const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
-    acc_t accr[2][2], acci[2][2];
+    acc_t accr[WM][WN], acci[WM][WN];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < WM; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) {
+      for (int y = 0; y < WN; ++y) {
         accr[x][y] = acc_t{0, 0, 0, 0};
         acci[x][y] = acc_t{0, 0, 0, 0};
       }
-    double pa_r[4], pa_i[4], pb_r[4], pb_i[4];
+    double pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
     auto fetch = [&](int64_t k0) {
+      const int64_t ka = kend - k0 - ak0, kb = kend - k0 - bk0;   // k positions left
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t gm = m0 + a_m[r], gk = k0 + a_k[r];
+      for (int r = 0; r < NA; ++r) {
         pa_r[r] = 0.0;
         pa_i[r] = 0.0;
-        if (gm < g.M && gk < kend) {
-          const int64_t o = gm * g.asm_ + gk * g.ask;
+        if (r * AMS < a_mrem && r * AKS < ka) {
+          const int64_t o = a_off + k0 * g.ask + r * a_rs;
           pa_r[r] = Ar[o];
           if (AC) pa_i[r] = Ai[o];
         }
-        const int64_t gn = n0 + b_n[r], gk2 = k0 + b_k[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
         pb_r[r] = 0.0;
         pb_i[r] = 0.0;
-        if (gn < g.N && gk2 < kend) {
-          const int64_t o = gk2 * g.bsk + gn * g.bsn;
+        if (r * BNS < b_nrem && r * BKS < kb) {
+          const int64_t o = b_off + k0 * g.bsk + r * b_rs;
           pb_r[r] = Br[o];
           if (BC) pb_i[r] = Bi[o];
         }
@@ -167,11 +180,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     };
     auto stage = [&](int buf) {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        (&sa_r[buf][0][0])[A_at(a_k[r], a_m[r])] = (T)pa_r[r];
-        if (AC) (&sa_i[buf][0][0])[A_at(a_k[r], a_m[r])] = (T)pa_i[r];
-        (&sb_r[buf][0][0])[B_at(b_k[r], b_n[r])] = (T)pb_r[r];
-        if (BC) (&sb_i[buf][0][0])[B_at(b_k[r], b_n[r])] = (T)pb_i[r];
+      for (int r = 0; r < NA; ++r) {
+        (&sa_r[buf][0][0])[lda0 + r * ldas] = (T)pa_r[r];
+        if (AC) (&sa_i[buf][0][0])[lda0 + r * ldas] = (T)pa_i[r];
+      }
+#pragma unroll
+      for (int r = 0; r < NB; ++r) {
+        (&sb_r[buf][0][0])[ldb0 + r * ldbs] = (T)pb_r[r];
+        if (BC) (&sb_i[buf][0][0])[ldb0 + r * ldbs] = (T)pb_i[r];
       }
     };
     if (kbeg < kend) {
@@ -183,23 +199,28 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
       const bool more = k0 + BK < kend;
       if (more) fetch(k0 + BK);
-#pragma unroll
+      // Wide tiles keep fragments of one (float64) or two (float32) k-steps in
+      // flight instead of four: the accumulators fill most of the register file.
+#pragma unroll (WM * WN <= 4 ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
-        T a_r[2], a_i[2], b_r[2], b_i[2];
+        T a_r[WM], a_i[WM], b_r[WN], b_i[WN];
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
-          const int ia = A_at(kr, wm * 32 + x * 16 + (lane & 15));
-          const int ib = B_at(kr, wn * 32 + x * 16 + (lane & 15));
+        for (int x = 0; x < WM; ++x) {
+          const int ia = A_at(kr, wm * 16 * WM + x * 16 + (lane & 15));
           a_r[x] = (&sa_r[buf][0][0])[ia];
           a_i[x] = AC ? (&sa_i[buf][0][0])[ia] : (T)0;
-          b_r[x] = (&sb_r[buf][0][0])[ib];
-          b_i[x] = BC ? (&sb_i[buf][0][0])[ib] : (T)0;
         }
 #pragma unroll
-        for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < WN; ++y) {
+          const int ib = B_at(kr, wn * 16 * WN + y * 16 + (lane & 15));
+          b_r[y] = (&sb_r[buf][0][0])[ib];
+          b_i[y] = BC ? (&sb_i[buf][0][0])[ib] : (T)0;
+        }
 #pragma unroll
-          for (int y = 0; y < 2; ++y) {
+        for (int x = 0; x < WM; ++x)
+#pragma unroll
+          for (int y = 0; y < WN; ++y) {
             accr[x][y] = Mfma<T>::mma(a_r[x], b_r[y], accr[x][y]);
             if (AC && BC) {
               accr[x][y] = Mfma<T>::mma(-a_i[x], b_i[y], accr[x][y]);
@@ -222,13 +243,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     double* Ci = (AC || BC) ? (split ? g.pi + (int64_t)blockIdx.y * g.M * g.N : g.ci + b * g.csb) : nullptr;
     const int64_t sm = split ? g.N : g.csm, sn = split ? 1 : g.csn;
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < WM; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y)
+      for (int y = 0; y < WN; ++y)
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * 32 + x * 16 + Mfma<T>::row(lane, r);
-          const int64_t gn = n0 + wn * 32 + y * 16 + (lane & 15);
+          const int64_t gm = m0 + wm * 16 * WM + x * 16 + Mfma<T>::row(lane, r);
+          const int64_t gn = n0 + wn * 16 * WN + y * 16 + (lane & 15);
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * sm + gn * sn;
             if (split) {
@@ -707,12 +728,51 @@ __global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t*
   }
 }
 
+// Tile shapes of gemm_mfma: 0 = 64x64, 1 = 64x128, 2 = 128x64, 3 = 128x128.
+constexpr int kTiles = 4;
+constexpr int kTileM[kTiles] = {64, 64, 128, 128}, kTileN[kTiles] = {64, 128, 64, 128};
+
+// Complex x complex keeps 64x64 (four MFMAs per staged fragment pair already).
+// A complex x real product widens only the real operand's side: widening the
+// complex side doubles two planes and leaves LDS for one work-group per CU.
+// 128x128 holds 16 accumulator blocks: real x real in float32 only (in float64
+// they exceed the registers of two waves per SIMD).  The bf16x3 kernel has one
+// tile shape.
+inline bool tile_allowed(int v, int prec, bool ac, bool bc) {
+  if (v < 0 || v >= kTiles) return false;
+  if (prec == 2 || (ac && bc)) return v == 0;
+  if (ac) return v == 0 || v == 1;
+  if (bc) return v == 0 || v == 2;
+  return v < 3 || prec == 1;
+}
+
+template <typename T, bool AC, bool BC, int WM, int WN>
+void launch_mfma_tile(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (akc && bkc) gemm_mfma<T, AC, BC, true, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else if (akc) gemm_mfma<T, AC, BC, true, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else if (bkc) gemm_mfma<T, AC, BC, false, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else gemm_mfma<T, AC, BC, false, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
+}
+
 template <typename T, bool AC, bool BC>
-void launch_mfma(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if (akc && bkc) gemm_mfma<T, AC, BC, true, true><<<grid, kThreads, 0, st>>>(g);
-  else if (akc) gemm_mfma<T, AC, BC, true, false><<<grid, kThreads, 0, st>>>(g);
-  else if (bkc) gemm_mfma<T, AC, BC, false, true><<<grid, kThreads, 0, st>>>(g);
-  else gemm_mfma<T, AC, BC, false, false><<<grid, kThreads, 0, st>>>(g);
+void launch_mfma(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if constexpr (AC && BC) {
+    launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+  } else if constexpr (AC) {
+    if (v == 1) launch_mfma_tile<T, AC, BC, 2, 4>(grid, st, g, akc, bkc);
+    else launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+  } else if constexpr (BC) {
+    if (v == 2) launch_mfma_tile<T, AC, BC, 4, 2>(grid, st, g, akc, bkc);
+    else launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+  } else {
+    if (v == 1) launch_mfma_tile<T, AC, BC, 2, 4>(grid, st, g, akc, bkc);
+    else if (v == 2) launch_mfma_tile<T, AC, BC, 4, 2>(grid, st, g, akc, bkc);
+    else if (v == 3 && sizeof(T) == 4) {
+      if constexpr (sizeof(T) == 4) launch_mfma_tile<T, AC, BC, 4, 4>(grid, st, g, akc, bkc);
+    } else {
+      launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+    }
+  }
 }
 
 template <bool AC, bool BC>
@@ -724,10 +784,18 @@ void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool 
 }
 
 template <bool AC, bool BC>
-void launch_prec(int prec, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if (prec == 0) launch_mfma<double, AC, BC>(grid, st, g, akc, bkc);
-  else if (prec == 1) launch_mfma<float, AC, BC>(grid, st, g, akc, bkc);
+void launch_prec(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (prec == 0) launch_mfma<double, AC, BC>(v, grid, st, g, akc, bkc);
+  else if (prec == 1) launch_mfma<float, AC, BC>(v, grid, st, g, akc, bkc);
   else launch_bf16x3<AC, BC>(grid, st, g, akc, bkc);
+}
+
+void launch_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc, bool akc,
+                 bool bkc) {
+  if (ac && bc) launch_prec<true, true>(prec, v, grid, st, g, akc, bkc);
+  else if (ac) launch_prec<true, false>(prec, v, grid, st, g, akc, bkc);
+  else if (bc) launch_prec<false, true>(prec, v, grid, st, g, akc, bkc);
+  else launch_prec<false, false>(prec, v, grid, st, g, akc, bkc);
 }
 
 int grid_for(int64_t n, int per_block = 256) {
@@ -743,6 +811,7 @@ class HipBackend : public Backend {
     for (auto& e : pool_) (void)hipEventDestroy(e);
     for (auto& g : graphs_) (void)hipGraphDestroy(g);
     for (auto& e : graph_timed_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+    if (tune_a_) { (void)hipEventDestroy(tune_a_); (void)hipEventDestroy(tune_b_); }
     if (own_stream_) (void)hipStreamDestroy(stream_);
   }
   bool own_stream_ = false;
@@ -853,25 +922,105 @@ class HipBackend : public Backend {
       g.pr = op.partial;
       g.pi = cplx ? op.partial + (int64_t)g.splitk * op.M * op.N : nullptr;
     }
-    const int64_t tiles = g.tiles_m * g.tiles_n;
-    if (tiles > 0x7fffffffLL) {
-      set_err("gemm: too many tiles");
-      return;
-    }
-    dim3 grid((unsigned)tiles, (unsigned)(g.splitk > 1 ? g.splitk : std::min<int64_t>(op.batch, 65535)));
-    begin();
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
-    if (ac && bc) launch_prec<true, true>(op.prec, grid, stream_, g, akc, bkc);
-    else if (ac) launch_prec<true, false>(op.prec, grid, stream_, g, akc, bkc);
-    else if (bc) launch_prec<false, true>(op.prec, grid, stream_, g, akc, bkc);
-    else launch_prec<false, false>(op.prec, grid, stream_, g, akc, bkc);
+    const int v = choose_tile(op, g, ac, bc, akc, bkc);
+    if (v < 0) return;
+    dim3 grid;
+    if (!shape_grid(g, v, op.batch, &grid)) return;
+    begin();
+    launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
     launched("gemm");
     if (g.splitk > 1) {
       splitk_reduce<<<grid_for(op.M * op.N), 256, 0, stream_>>>(g, cplx ? 1 : 0);
       launched("splitk_reduce");
     }
     end();
+  }
+
+  void set_tuning(int on) override { tuning_ = on != 0; }
+  void force_tile(int v) override { force_ = v; }
+
+  // Grid of tile shape v (tiles x split or batch); false on overflow.
+  bool shape_grid(GemmArgs& g, int v, int64_t batch, dim3* grid) {
+    g.tiles_m = (g.M + kTileM[v] - 1) / kTileM[v];
+    g.tiles_n = (g.N + kTileN[v] - 1) / kTileN[v];
+    const int64_t tiles = g.tiles_m * g.tiles_n;
+    if (tiles > 0x7fffffffLL) {
+      set_err("gemm: too many tiles");
+      return false;
+    }
+    *grid = dim3((unsigned)tiles, (unsigned)(g.splitk > 1 ? g.splitk : std::min<int64_t>(batch, 65535)));
+    return true;
+  }
+
+  // Work-per-byte rule: MFMA products per staged operand word, capped where
+  // the complex x complex 64x64 tile runs at the matrix-core peak, times the
+  // fill of the last round of work-groups (two resident per CU).
+  static double rule_score(const GemmArgs& g, int v, int64_t batch, bool ac, bool bc) {
+    const double tm = kTileM[v], tn = kTileN[v];
+    const double prods = (ac && bc) ? 4.0 : ((ac || bc) ? 2.0 : 1.0);
+    const double words = tm * (ac ? 2 : 1) + tn * (bc ? 2 : 1);
+    const double intensity = std::min(1.0, tm * tn * prods / words / 64.0);
+    const double units = (double)((g.M + kTileM[v] - 1) / kTileM[v]) * ((g.N + kTileN[v] - 1) / kTileN[v]) *
+                         (double)(g.splitk > 1 ? g.splitk : batch);
+    const double slots = 2.0 * 256.0;
+    const double rounds = std::ceil(units / slots);
+    return intensity * units / (rounds * slots);
+  }
+
+  int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc) {
+    if (force_ >= 0) return tile_allowed(force_, op.prec, ac, bc) ? force_ : 0;
+    int cand[kTiles], nc = 0;
+    for (int v = 0; v < kTiles; ++v)
+      if (tile_allowed(v, op.prec, ac, bc)) cand[nc++] = v;
+    if (nc == 1) return cand[0];
+    const std::array<int64_t, 10> key = {op.prec, op.M, op.N, op.K, op.batch, (int64_t)ac, (int64_t)bc,
+                                         (int64_t)akc, (int64_t)bkc, (int64_t)g.splitk};
+    auto it = tuned_.find(key);
+    if (it != tuned_.end()) return it->second;
+    if (!tuning_ || capturing_) {
+      int best = cand[0];
+      double bs = -1.0;
+      for (int i = 0; i < nc; ++i) {
+        const double sc = rule_score(g, cand[i], op.batch, ac, bc);
+        if (sc > bs + 1e-9) { bs = sc; best = cand[i]; }
+      }
+      return best;
+    }
+    // Time every candidate on this product with alpha = 0: C (beta = 1) keeps
+    // its value, a beta = 0 output and split partials are rewritten by the
+    // launch that follows.  Short products are timed twice.
+    if (!tune_a_) {
+      record(hipEventCreate(&tune_a_), "hipEventCreate");
+      record(hipEventCreate(&tune_b_), "hipEventCreate");
+    }
+    GemmArgs gt = g;
+    gt.alpha = 0.0;
+    float best_ms[kTiles];
+    for (int i = 0; i < nc; ++i) best_ms[i] = 1e30f;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < nc; ++i) {
+        dim3 grid;
+        if (!shape_grid(gt, cand[i], op.batch, &grid)) return -1;
+        record(hipEventRecord(tune_a_, stream_), "hipEventRecord");
+        launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
+        launched("gemm (tuning)");
+        record(hipEventRecord(tune_b_, stream_), "hipEventRecord");
+        record(hipEventSynchronize(tune_b_), "hipEventSynchronize");
+        float ms = 0.f;
+        record(hipEventElapsedTime(&ms, tune_a_, tune_b_), "hipEventElapsedTime");
+        best_ms[i] = std::min(best_ms[i], ms);
+      }
+      float fastest = 1e30f;
+      for (int i = 0; i < nc; ++i) fastest = std::min(fastest, best_ms[i]);
+      if (fastest >= 2.0f) break;
+    }
+    int bi = 0;
+    for (int i = 1; i < nc; ++i)
+      if (best_ms[i] < best_ms[bi]) bi = i;
+    tuned_[key] = cand[bi];
+    return cand[bi];
   }
 
   void permute(const PermOp& op) override {
@@ -988,6 +1137,10 @@ class HipBackend : public Backend {
   std::vector<Timed> done_;
   std::vector<Timed> graph_timed_;
   std::vector<hipEvent_t> pool_;
+  std::map<std::array<int64_t, 10>, int> tuned_;   // tile shape per GEMM signature
+  bool tuning_ = true;
+  int force_ = -1;
+  hipEvent_t tune_a_ = nullptr, tune_b_ = nullptr;
   hipEvent_t cur_a_ = nullptr;
   bool timing_ = false;
   hipEvent_t event() {

@@ -550,7 +550,7 @@ struct Context {
 
   // Fixed-pass steps may be captured once into a graph and replayed: every
   // argument of a step is either constant or read from device memory.
-  bool graph_mode() const { return opt.reserved0 != 0 && opt.fp_fixed_iters > 0; }
+  bool graph_mode() const { return opt.graph != 0 && opt.fp_fixed_iters > 0; }
   void* graph_for(double dt) {
     if (step_graph && graph_dt == dt) return step_graph;
     if (step_graph) {
@@ -662,6 +662,7 @@ bool valid_options(const rteom_options* o, std::string* m) {
   if (o->fp_fixed_iters < 0 || o->fp_max_iter < 1) { *m = "bad pass counts"; return false; }
   if (!(o->fp_tol > 0.0)) { *m = "fp_tol must be positive"; return false; }
   if (o->max_steps < 1) { *m = "max_steps must be >= 1"; return false; }
+  if (o->tune < 0 || o->tune > 1 || o->reserved1 != 0) { *m = "tune must be 0 or 1, reserved1 0"; return false; }
   return true;
 }
 
@@ -690,6 +691,7 @@ void rteom_default_options(rteom_options* o) {
   o->fp_tol = 1e-10;
   o->dC_include_fT1 = 1;
   o->max_steps = 100000;
+  o->tune = 1;
 }
 
 // Plan init + one residual without touching a device: the workspace peak and the

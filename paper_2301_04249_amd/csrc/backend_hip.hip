@@ -954,19 +954,19 @@ class HipBackend : public Backend {
     return true;
   }
 
-  // Work-per-byte rule: MFMA products per staged operand word, capped where
-  // the complex x complex 64x64 tile runs at the matrix-core peak, times the
-  // fill of the last round of work-groups (two resident per CU).
-  static double rule_score(const GemmArgs& g, int v, int64_t batch, bool ac, bool bc) {
+  // Rule used without timing: estimated time = rounds of work-groups over the
+  // 256 CUs (two resident work-groups share one CU's matrix cores) times the
+  // tile area over an efficiency that grows weakly with the MFMA products per
+  // staged operand word (the complex x complex 64x64 tile runs at 64).  Wider
+  // tiles only pay off over long sums, so they are considered from K >= 4096.
+  static double rule_time(const GemmArgs& g, int v, int64_t batch, bool ac, bool bc) {
     const double tm = kTileM[v], tn = kTileN[v];
     const double prods = (ac && bc) ? 4.0 : ((ac || bc) ? 2.0 : 1.0);
     const double words = tm * (ac ? 2 : 1) + tn * (bc ? 2 : 1);
-    const double intensity = std::min(1.0, tm * tn * prods / words / 64.0);
+    const double eff = std::pow(std::min(1.0, tm * tn * prods / words / 64.0), 0.3);
     const double units = (double)((g.M + kTileM[v] - 1) / kTileM[v]) * ((g.N + kTileN[v] - 1) / kTileN[v]) *
                          (double)(g.splitk > 1 ? g.splitk : batch);
-    const double slots = 2.0 * 256.0;
-    const double rounds = std::ceil(units / slots);
-    return intensity * units / (rounds * slots);
+    return std::ceil(units / 256.0) * (tm * tn / 4096.0) / eff;
   }
 
   int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc) {
@@ -981,10 +981,10 @@ class HipBackend : public Backend {
     if (it != tuned_.end()) return it->second;
     if (!tuning_ || capturing_) {
       int best = cand[0];
-      double bs = -1.0;
-      for (int i = 0; i < nc; ++i) {
-        const double sc = rule_score(g, cand[i], op.batch, ac, bc);
-        if (sc > bs + 1e-9) { bs = sc; best = cand[i]; }
+      double bt = rule_time(g, cand[0], op.batch, ac, bc);
+      for (int i = 1; i < nc && g.kchunk >= 4096; ++i) {
+        const double t = rule_time(g, cand[i], op.batch, ac, bc);
+        if (t < bt * 0.98) { bt = t; best = cand[i]; }
       }
       return best;
     }

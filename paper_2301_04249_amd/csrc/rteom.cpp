@@ -798,7 +798,16 @@ rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t
     c.ws_owned = true;
     c.arena.init(static_cast<char*>(c.ws), need);
   }
-  st = guarded(ctx.get(), [&] { c.init(fock_diag, chol); });
+  c.be->set_tuning(o.tune);
+  st = guarded(ctx.get(), [&] {
+    c.init(fock_diag, chol);
+    // Graph-captured steps cannot time GEMM tile shapes: tune them now on one
+    // residual evaluation (at T = 0; only shapes matter), outside any capture.
+    if (o.tune && c.graph_mode()) {
+      c.residual(c.X, c.R);
+      c.be->sync();
+    }
+  });
   if (st != RTEOM_OK) {
     g_last_error = c.err;
     if (c.ws_owned) c.be->release(c.ws);

@@ -144,6 +144,25 @@ def test_graph_replay_matches_direct_launches():
     assert np.array_equal(a.get_amplitudes()[1], b.get_amplitudes()[1])
 
 
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_tile_shape_choice_is_bit_identical(prec):
+    """GEMM tile shapes differ only in how output tiles are assigned to work-groups: the
+    timed tile choice and the rule's choice give bitwise the same residual and C(t) on the
+    formaldehyde-shaped system (where wide tiles are candidates)."""
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1)
+    r = []
+    for tune in (True, False):
+        P = _prop(eps, chol, 8, 8, 0, 1, prec=prec, fixed_iters=2, tune=tune)
+        b1, b2 = blocks.random_block_amplitudes(*P.t1_shape()[1:], seed=5, scale=1e-3)
+        P.set_amplitudes(b1, b2)
+        r.append(P.residual())
+        P.step(0.025, 2)
+        r.append(P.cumulant()[1])
+        P.close()
+    assert np.array_equal(r[0][0], r[2][0]) and np.array_equal(r[0][1], r[2][1])
+    assert np.array_equal(r[1], r[3])
+
+
 def test_batch_of_uneven_systems_matches_sequential():
     """Three uneven core-hole systems in one graph launch per step equal their separate runs."""
     shapes = [Shape(3, 9, 20), Shape(4, 14, 40), Shape(5, 11, 30)]

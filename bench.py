@@ -21,7 +21,7 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from synthetic import ESCA_PAPER, FORMALDEHYDE, TINY, draw_system  # noqa: E402
+from synthetic import ESCA_PAPER, FORMALDEHYDE, TINY, batched_shapes, draw_system  # noqa: E402
 
 # Ladder kernel per precision (the contraction's MFMA instruction family)
 KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float>", "bf16x3": "gemm_bf16x3"}
@@ -35,6 +35,9 @@ TRAFFIC = {
     ("esca", "fp64"): 1.0151e13,
 }
 
+DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",
+         "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}
+
 # MI355X published peaks (dense)
 PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
 PEAK_HBM_GBS = 8000.0
@@ -42,6 +45,9 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     "formaldehyde": dict(shape=FORMALDEHYDE, cfg=1, dt=0.025, passes=3, steps=4,
                          desc="formaldehyde-shaped core hole: o=8, v=110 per spin, Q=600, beta hole, dt=0.025 au"),
+    "batched": dict(batch=16, cfg=2, dt=0.025, passes=2, steps=20, cpu_sample="formaldehyde",
+                    desc="16 independent core holes of uneven shape (o in [5,20], v in [40,200] per spin, "
+                         "Q = 4 v, beta holes), one graph launch per time step for all, dt=0.025 au"),
     "tiny": dict(shape=TINY, cfg=0, dt=0.025, passes=3, steps=4,
                  desc="tiny: o=4, v=16 per spin, Q=48, beta hole, dt=0.025 au"),
     # the paper's ESCA run: 71 occupied / 649 virtual spin-orbitals in total
@@ -74,6 +80,107 @@ def cpu_baseline(name, eps, chol, flops_per_residual):
             "sample": f"one residual evaluation R(T) of the {name} workload (o={shape.o}, v={shape.v} per spin, "
                       f"Q={shape.nchol}) at seeded amplitudes (spin-orbital oracle, lean integral blocks): "
                       f"{dt:.2f} s; rate = the GPU path's flop count of that residual / that time"}
+
+
+def run_batch(args, work):
+    """Batched workload: all systems advance together, one graph launch per time step (timed
+    region 1, the value); then the same systems one after another with direct launches and
+    HIP events around the ladder launches (timed region 2: roofline and the sequential time)."""
+    import torch
+    from paper_2301_04249_amd import rteom
+    shapes = batched_shapes(work["batch"], cfg=work["cfg"])
+    systems = [draw_system(sh, cfg=work["cfg"], sys_id=k) for k, sh in enumerate(shapes)]
+    dt, passes = work["dt"], work["passes"]
+    print(f"[bench] workload batched: {len(shapes)} systems", file=sys.stderr, flush=True)
+
+    def props(graph):
+        out = []
+        for sh, (eps, chol) in zip(shapes, systems):
+            out.append(rteom.Propagator(eps, chol, sh.o, sh.o, 0, 1, prec=args.prec, fixed_iters=passes,
+                                        workspace="torch", max_steps=args.steps + args.warmup + 4, graph=graph))
+        return out
+
+    ps = props(True)
+    flops_res = [p.residual_flops() for p in ps]
+    B = rteom.Batch(ps)
+    print("[bench] batch ready", file=sys.stderr, flush=True)
+    if args.warmup:
+        B.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    B.step(dt, args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    print(f"[bench] batched: {(t1 - t0) * 1e3 / args.steps:.2f} ms/step", file=sys.stderr, flush=True)
+    for p in ps:
+        if not np.all(np.isfinite(p.cumulant()[1])):
+            print("bench.py: non-finite C(t)", file=sys.stderr)
+            return 3
+    B.close()
+    for p in ps:
+        p.close()
+    del B, ps
+    # region 2: sequential, direct launches, ladder timed
+    qs = props(False)
+    for q in qs:
+        q.profile(("ladder",))
+        if args.warmup:
+            q.step(dt, args.warmup)
+    torch.cuda.synchronize()
+    for q in qs:
+        for ph in rteom.PHASES:
+            q.phase_stats(ph)
+    torch.cuda.synchronize()
+    u0 = time.perf_counter()
+    for q in qs:
+        q.step(dt, args.steps)
+    torch.cuda.synchronize()
+    u1 = time.perf_counter()
+    lad_ms = lad_flop_total = 0.0
+    lad_ops = 0
+    for q in qs:
+        ms, ops, fl = q.phase_stats("ladder")
+        lad_ms += ms
+        lad_ops += ops
+        lad_flop_total += fl * ops
+    for q in qs:
+        q.close()
+    del qs
+    n_res = passes * args.steps
+    total = sum(flops_res) * n_res
+    value = total / (t1 - t0) / 1e12
+    achieved = lad_flop_total / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
+    peak = PEAK_TFLOPS[args.prec]
+    out = {
+        "metric": "residual TFLOP/s (time step of the RT-EOM-CCSD hot path)",
+        "value": round(value, 4), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round((t1 - t0) * 1e3 / args.steps, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": DTYPE[args.prec],
+        "data": "synthetic (seeded eps and Cholesky vectors of the stated shapes)",
+        "config": {"workload": work["desc"], "systems": [[sh.o, sh.v, sh.nchol] for sh in shapes],
+                   "passes_per_step": passes, "residuals_timed": n_res * len(shapes),
+                   "launch": "graph (one launch of a graph holding every system's captured step)",
+                   "flops_per_step": sum(flops_res) * passes,
+                   "ms_per_step_sequential_direct": round((u1 - u0) * 1e3 / args.steps, 4),
+                   "speedup_vs_sequential_direct": round((u1 - u0) / (t1 - t0), 4)},
+        "roofline": {"kernel": KERNEL_NAME[args.prec] + " particle-particle ladders of all systems",
+                     "bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 5), "traffic": TRAFFIC.get(("batched", args.prec)),
+                     "launches": lad_ops, "flops_per_launch": lad_flop_total / lad_ops if lad_ops else None,
+                     "timing": "HIP events around each ladder launch in a second timed region: the same systems "
+                               "and steps one after another with direct launches"},
+    }
+    if not args.no_cpu_baseline:
+        name = work["cpu_sample"]
+        sw = WORKLOADS[name]
+        eps, chol = draw_system(sw["shape"], cfg=sw["cfg"])
+        Q = rteom.Propagator(eps, chol, sw["shape"].o, sw["shape"].o, 0, 1, prec=args.prec,
+                             fixed_iters=sw["passes"], workspace="torch", max_steps=2)
+        f = Q.residual_flops()
+        Q.close()
+        out["cpu_baseline"] = cpu_baseline(name, eps, chol, f)
+    print(json.dumps(out), flush=True)
+    return 0
 
 
 def main(argv=None):
@@ -109,6 +216,8 @@ def main(argv=None):
     work = WORKLOADS[args.workload]
     if args.steps is None:
         args.steps = work["steps"]
+    if work.get("batch"):
+        return run_batch(args, work)
     shape = work["shape"]
     eps, chol = draw_system(shape, cfg=work["cfg"])
     print(f"[bench] workload {args.workload}: {work['desc']}", file=sys.stderr, flush=True)
@@ -185,8 +294,7 @@ def main(argv=None):
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": {"fp64": "f64", "fp32": "f32 contractions, f64 update",
-                  "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}[args.prec],
+        "dtype": DTYPE[args.prec],
         "data": "synthetic (seeded eps and Cholesky vectors of the stated shape)",
         "config": config,
         "roofline": {"kernel": KERNEL_NAME[args.prec] + " particle-particle ladder (3 spin blocks in one launch)",

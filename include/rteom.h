@@ -120,6 +120,23 @@ rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* mic
 rteom_status rteom_cumulant(const rteom_ctx* ctx, int64_t cap, double* t_out, double* c_out,
                             int64_t* n_out);
 
+/* Spectral function of the core hole from the device C(t) history (Sec. 2.2: the
+   cumulant form of the core Green's function, Eqs. cum_gf and cum_gf2):
+     G(t_k) = -i exp(-i (eps_c + e_corr) t_k) exp(C(t_k)),
+     A(w)   = -(1/pi) Im sum_k w_k exp(i w t_k - eta t_k) G(t_k),
+   with eps_c the Fock-diagonal entry of the ionised orbital given to rteom_init,
+   e_corr the N-electron correlation energy (a constant shift; 0 if unknown), w_k
+   the trapezoid weights of the time grid and eta >= 0 a damping (Lorentzian
+   broadening).  omega: host [n_w] frequencies (Eh), ascending and uniformly
+   spaced for the peak refinement; a_out: host [n_w] A(omega).  qp_out (nullable):
+   host [2] = (position of the largest A, refined by the parabola through the
+   grid maximum and its two neighbours; A at the grid maximum).  Computed on the
+   device (temporary device memory of (3 n + 2 n_w + 2) doubles, n = steps + 1);
+   synchronises the stream.  ARG for NULL omega/a_out, n_w < 1, non-finite
+   input or eta < 0; OOM if the temporary cannot be allocated. */
+rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                            double* a_out, double* qp_out);
+
 /* Extended-space sizes and orbital lists: occ_list [n_o], vir_list [n_v] (nullable). */
 rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_t* occ_list,
                         int32_t* vir_list);

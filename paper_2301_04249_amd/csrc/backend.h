@@ -134,6 +134,12 @@ class Backend {
   // *step = k + 1.  c_hist, e_hist: device (re, im) pairs; e_next: device pair.
   virtual void cumulant_append(double* c_hist, double* e_hist, const double* e_next,
                                int64_t* step, double h) = 0;
+  // Spectral function from the cumulant history (all pointers device memory):
+  // c_hist [n][2] C(t_k), times [n], omega [n_w] -> a_out [n_w] A(omega),
+  // qp_out [2] = (refined position of the largest A, A at the grid maximum);
+  // shift = eps_c + E_N^corr, eta = damping; wg is scratch of 2 n doubles.
+  virtual void spectral(const double* c_hist, const double* times, int64_t n, double shift, double eta,
+                        const double* omega, int64_t n_w, double* wg, double* a_out, double* qp_out) = 0;
   // Stream capture of a fixed sequence of operations into a replayable graph
   // (returns false where not supported: the caller then issues operations directly).
   virtual bool begin_capture() { return false; }

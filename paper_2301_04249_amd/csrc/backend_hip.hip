@@ -728,6 +728,74 @@ __global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t*
   }
 }
 
+// ---------------------------------------------------------------------------
+// Spectral function (post-processing of C(t)).  G(t_k) = -i e^{-i s t_k} e^{C(t_k)}
+// with s = eps_c + E_N^corr, times its trapezoid weight on the (possibly
+// non-uniform) time grid; then A(w) = -(1/pi) Im sum_k wG_k e^{i w t_k - eta t_k},
+// one frequency per thread, summed in k order; then the largest A on one block.
+__global__ void green_kernel(const double* c, const double* t, int64_t n, double shift, double* wg) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  double w = 0.0;
+  if (n > 1) w = 0.5 * ((k + 1 < n ? t[k + 1] : t[k]) - (k > 0 ? t[k - 1] : t[k]));
+  const double mag = exp(c[2 * k]) * w, ph = c[2 * k + 1] - shift * t[k];
+  double sn, cs;
+  sincos(ph, &sn, &cs);
+  wg[2 * k] = mag * sn;          // -i e^{i ph}
+  wg[2 * k + 1] = -mag * cs;
+}
+
+__global__ void spectrum_kernel(const double* wg, const double* t, int64_t n, double eta, const double* omega,
+                                int64_t n_w, double* a) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n_w) return;
+  const double w = omega[j];
+  double im = 0.0;
+  for (int64_t k = 0; k < n; ++k) {
+    double sn, cs;
+    sincos(w * t[k], &sn, &cs);
+    im += exp(-eta * t[k]) * (wg[2 * k] * sn + wg[2 * k + 1] * cs);
+  }
+  a[j] = -im / M_PI;
+}
+
+constexpr int kPeakThreads = 1024;
+__global__ __launch_bounds__(kPeakThreads) void qp_kernel(const double* a, const double* omega, int64_t n_w,
+                                                          double* qp) {
+  __shared__ double sv[kPeakThreads];
+  __shared__ int64_t si[kPeakThreads];
+  double best = -INFINITY;
+  int64_t bi = -1;
+  for (int64_t j = threadIdx.x; j < n_w; j += kPeakThreads)
+    if (a[j] > best || bi < 0) { best = a[j]; bi = j; }   // first index of the maximum in this stride
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int off = kPeakThreads / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      const double ov = sv[threadIdx.x + off];
+      const int64_t oi = si[threadIdx.x + off];
+      if (oi >= 0 && (si[threadIdx.x] < 0 || ov > sv[threadIdx.x] ||
+                      (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int64_t k = si[0];
+    double pos = omega[k];
+    if (k > 0 && k + 1 < n_w) {
+      const double y0 = a[k - 1], y1 = a[k], y2 = a[k + 1], den = y0 - 2.0 * y1 + y2;
+      const double sh = den != 0.0 ? 0.5 * (y0 - y2) / den : 0.0;
+      pos = omega[k] + sh * (omega[1] - omega[0]);
+    }
+    qp[0] = pos;
+    qp[1] = a[k];
+  }
+}
+
 // Tile shapes of gemm_mfma: 0 = 64x64, 1 = 64x128, 2 = 128x64, 3 = 128x128.
 constexpr int kTiles = 4;
 constexpr int kTileM[kTiles] = {64, 64, 128, 128}, kTileN[kTiles] = {64, 128, 64, 128};
@@ -1077,6 +1145,17 @@ class HipBackend : public Backend {
     cumulant_kernel<<<1, 64, 0, stream_>>>(c, e, en, step, h);
     launched("cumulant");
     end();
+  }
+
+  void spectral(const double* c_hist, const double* times, int64_t n, double shift, double eta, const double* omega,
+                int64_t n_w, double* wg, double* a_out, double* qp_out) override {
+    if (n < 1 || n_w < 1) return;
+    green_kernel<<<grid_for(n), 256, 0, stream_>>>(c_hist, times, n, shift, wg);
+    launched("green");
+    spectrum_kernel<<<(unsigned)((n_w + 255) / 256), 256, 0, stream_>>>(wg, times, n, eta, omega, n_w, a_out);
+    launched("spectrum");
+    qp_kernel<<<1, kPeakThreads, 0, stream_>>>(a_out, omega, n_w, qp_out);
+    launched("qp");
   }
 
   void* stream() override { return stream_; }

@@ -189,6 +189,32 @@ class HostBackend : public Backend {
     e.e_out[1] = ei;
   }
 
+  void spectral(const double* c, const double* t, int64_t n, double shift, double eta, const double* omega,
+                int64_t n_w, double* wg, double* a, double* qp) override {
+    if (n < 1 || n_w < 1) return;
+    for (int64_t k = 0; k < n; ++k) {
+      const double w = n > 1 ? 0.5 * ((k + 1 < n ? t[k + 1] : t[k]) - (k > 0 ? t[k - 1] : t[k])) : 0.0;
+      const double mag = std::exp(c[2 * k]) * w, ph = c[2 * k + 1] - shift * t[k];
+      wg[2 * k] = mag * std::sin(ph);
+      wg[2 * k + 1] = -mag * std::cos(ph);
+    }
+    int64_t best = 0;
+    for (int64_t j = 0; j < n_w; ++j) {
+      double im = 0.0;
+      for (int64_t k = 0; k < n; ++k)
+        im += std::exp(-eta * t[k]) * (wg[2 * k] * std::sin(omega[j] * t[k]) + wg[2 * k + 1] * std::cos(omega[j] * t[k]));
+      a[j] = -im / M_PI;
+      if (a[j] > a[best]) best = j;
+    }
+    double pos = omega[best];
+    if (best > 0 && best + 1 < n_w) {
+      const double y0 = a[best - 1], y1 = a[best], y2 = a[best + 1], den = y0 - 2.0 * y1 + y2;
+      pos = omega[best] + (den != 0.0 ? 0.5 * (y0 - y2) / den : 0.0) * (omega[1] - omega[0]);
+    }
+    qp[0] = pos;
+    qp[1] = a[best];
+  }
+
   void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h) override {
     // C + i h (E_k + E_{k+1})
     const int64_t k = *step;

@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <new>
 #include <string>
@@ -77,6 +78,7 @@ struct Context {
   double* c_hist = nullptr;  // [(max_steps+1)][2]
   int64_t nsteps = 0;
   std::vector<double> times;
+  double eps_core = 0.0;               // N-electron orbital energy of the ionised orbital
   double res_flops = 0.0;
   double res_phase_flops[kNumPhases] = {0};
 
@@ -145,6 +147,7 @@ struct Context {
 
   void init(const double* eps, const double* chol) {
     setup_spaces();
+    if (eps) eps_core = eps[core_orb];
     eng.be = be;
     eng.scratch = &arena;
     eng.prec = RTEOM_FP64;   // integral blocks and Fock matrices: float64, once
@@ -849,6 +852,33 @@ rteom_status rteom_cumulant(const rteom_ctx* cctx, int64_t cap, double* t_out, d
     if (t_out)
       for (int64_t k = 0; k < n; ++k) t_out[k] = c.times[k];
     *n_out = n;
+  });
+}
+
+rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                            double* a_out, double* qp_out) {
+  if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  if (!omega || !a_out || n_w < 1) { c.err = "omega and a_out are required, n_w >= 1"; return RTEOM_ERR_ARG; }
+  if (!std::isfinite(e_corr) || !std::isfinite(eta) || eta < 0.0) {
+    c.err = "e_corr must be finite and eta finite and >= 0";
+    return RTEOM_ERR_ARG;
+  }
+  for (int64_t j = 0; j < n_w; ++j)
+    if (!std::isfinite(omega[j])) { c.err = "non-finite frequency"; return RTEOM_ERR_ARG; }
+  return guarded(ctx, [&] {
+    const int64_t n = c.nsteps + 1;
+    // post-processing buffers: times, frequencies, weighted G, A, peak
+    const size_t bytes = sizeof(double) * (size_t)(n + n_w + 2 * n + n_w + 2);
+    std::unique_ptr<double, std::function<void(double*)>> buf(
+        static_cast<double*>(c.be->alloc(bytes)), [&c](double* p) { if (p) c.be->release(p); });
+    if (!buf) throw Error(RTEOM_ERR_OOM, "device allocation for the spectrum failed");
+    double *t = buf.get(), *w = t + n, *wg = w + n_w, *a = wg + 2 * n, *qp = a + n_w;
+    c.be->h2d(t, c.times.data(), sizeof(double) * n);
+    c.be->h2d(w, omega, sizeof(double) * n_w);
+    c.be->spectral(c.c_hist, t, n, c.eps_core + e_corr, eta, w, n_w, wg, a, qp);
+    c.be->d2h(a_out, a, sizeof(double) * n_w);
+    if (qp_out) c.be->d2h(qp_out, qp, sizeof(double) * 2);
   });
 }
 

@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # every exported symbol of include/rteom.h
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
-    "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_spectral", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
     "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_batch_create", "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
@@ -82,6 +82,7 @@ def load(path: str = LIB_PATH):
                                c.c_int32, c.c_int32, c.POINTER(Options)]
     lib.rteom_step.argtypes = [c.c_void_p, c.c_double, c.c_int32, _ip]
     lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
+    lib.rteom_spectral.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
     lib.rteom_dims.argtypes = [c.c_void_p, _ip, _ip, _ip, _ip]
     lib.rteom_set_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
     lib.rteom_get_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
@@ -189,6 +190,15 @@ class Propagator:
         st = self.lib.rteom_cumulant(self.h, total, _ptr(t), _ptr(c), ctypes.byref(n))
         self._check(st, self.h)
         return t[: n.value], c[: n.value, 0] + 1j * c[: n.value, 1]
+
+    def spectral(self, omegas, eta, e_corr=0.0):
+        """(A(omega), qp position, A at the grid maximum) from the device C(t) (rteom_spectral)."""
+        w = np.ascontiguousarray(omegas, dtype=np.float64)
+        a = np.zeros(w.shape[0])
+        qp = np.zeros(2)
+        st = self.lib.rteom_spectral(self.h, float(e_corr), float(eta), w.shape[0], _ptr(w), _ptr(a), _ptr(qp))
+        self._check(st, self.h)
+        return a, qp[0], qp[1]
 
     def set_amplitudes(self, t1, t2):
         t1 = np.ascontiguousarray(t1, dtype=np.complex128).reshape(self.t1_shape())

@@ -4,6 +4,8 @@ Float64 path; the bound is relative 1e-11 on residual elements (rounding-order
 differences of float64 sums over <= 1e5 terms stay far below) and 1e-10 absolute
 on C(t) over the trajectories below (the FP64 target for C(t) is 1e-8).
 """
+import functools
+
 import numpy as np
 import pytest
 
@@ -82,10 +84,44 @@ def test_zero_amplitudes_residual_is_driver():
     assert P.energy() == 0
 
 
-@pytest.mark.parametrize("prec,res_tol,c_tol", [("fp32", 1e-5, 1e-6), ("bf16x3", 1e-3, 1e-4)])
-def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol):
+HARTREE_EV = 27.211386
+OMEGAS = np.arange(-26.0, -14.0, 0.001)   # Eh, around the core level eps_c = -20 Eh
+ETA = 0.01
+
+
+@functools.lru_cache(maxsize=1)
+def _tiny_reference():
+    """Oracle trajectory of the tiny workload: 200 steps, 3 fixed passes, dt = 0.025 au."""
+    eps, chol = draw_system(TINY, cfg=0)
+    sysm = reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1)
+    tr = propagate.propagate(sysm, 0.025, 200, fixed_iters=3)
+    a = propagate.spectral_function(tr.times, propagate.green_function(tr.times, tr.cumulant, eps[0]), OMEGAS, ETA)
+    return tr, a, propagate.qp_peak(OMEGAS, a)
+
+
+def test_spectral_function_parity():
+    """A(omega) and the QP peak computed on the device from the device C(t) (float64 path)
+    against the oracle's G(t), A(omega) and peak refinement, tiny workload, 200 steps."""
+    tr, a_ref, qp_ref = _tiny_reference()
+    eps, chol = draw_system(TINY, cfg=0)
+    P = _prop(eps, chol, 4, 4, 0, 1, fixed_iters=3)
+    P.step(0.025, 200)
+    a, qp, amax = P.spectral(OMEGAS, ETA)
+    err = np.abs(a - a_ref).max()
+    print(f"A(omega) max abs err {err:.3e} (max A {a_ref.max():.3e}); QP {qp:.9f} Eh vs oracle {qp_ref:.9f}")
+    assert err <= 1e-10 * np.abs(a_ref).max()
+    assert abs(qp - qp_ref) < 1e-9
+    assert amax == a.max()
+    # e_corr shifts the spectrum rigidly by -e_corr (Eq. cum_gf2)
+    a2, qp2, _ = P.spectral(OMEGAS + 0.3, ETA, e_corr=0.3)
+    assert np.abs(a2 - a).max() <= 1e-9 * np.abs(a).max()
+
+
+@pytest.mark.parametrize("prec,res_tol,c_tol,qp_tol_ev", [("fp32", 1e-5, 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-4, 1e-3)])
+def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol, qp_tol_ev):
     """float32 and bf16x3 contractions (float64 update and C(t)): residual relative Frobenius
-    error and C(t) max error against the oracle on the tiny workload (40 steps)."""
+    error, C(t) max error over the 200-step tiny trajectory and the QP peak shift in eV, all
+    against the oracle."""
     eps, chol = draw_system(TINY, cfg=0)
     sysm = reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1)
     P = _prop(eps, chol, 4, 4, 0, 1, prec=prec, fixed_iters=3)
@@ -97,14 +133,18 @@ def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol):
     rel = np.sqrt(np.sum(np.abs(r1 - e1) ** 2) + np.sum(np.abs(r2 - e2) ** 2)) / np.sqrt(
         np.sum(np.abs(e1) ** 2) + np.sum(np.abs(e2) ** 2))
     P.close()
+    tr, _, qp_ref = _tiny_reference()
     P = _prop(eps, chol, 4, 4, 0, 1, prec=prec, fixed_iters=3)
-    P.step(0.025, 40)
+    P.step(0.025, 200)
     _, c = P.cumulant()
-    ref = propagate.propagate(sysm, 0.025, 40, fixed_iters=3).cumulant
-    cerr = np.abs(c - ref).max()
-    print(f"{prec}: residual rel Frobenius {rel:.3e}, C(t) max abs err {cerr:.3e} (max |C| {np.abs(ref).max():.3e})")
+    cerr = np.abs(c - tr.cumulant).max()
+    _, qp, _ = P.spectral(OMEGAS, ETA)
+    shift = (qp - qp_ref) * HARTREE_EV
+    print(f"{prec}: residual rel Frobenius {rel:.3e}, C(t) max abs err {cerr:.3e} "
+          f"(max |C| {np.abs(tr.cumulant).max():.3e}), QP shift {shift:.3e} eV")
     assert rel < res_tol
     assert cerr < c_tol
+    assert abs(shift) < qp_tol_ev
 
 
 def test_formaldehyde_full_size_parity():

@@ -100,3 +100,21 @@ def test_residual_flops_known_at_init():
     assert f0 > 0
     P.residual(False)
     assert P.residual_flops() == f0
+
+
+def test_spectral_function_vs_oracle():
+    """rteom_spectral on the host engine: G, A(omega) and the QP peak against the oracle's
+    post-processing of the same C(t) (eps_c of the ionised orbital, trapezoid weights)."""
+    eps, chol = draw_system(Shape(3, 4, 10), cfg=4, chol_scale=2.0)
+    sysm = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, fixed_iters=3, lib_path=LIB)
+    P.step(0.05, 30)
+    t, c = P.cumulant()
+    w = np.arange(-25.0, -15.0, 0.01)
+    a, qp, amax = P.spectral(w, 0.05, e_corr=0.02)
+    a_ref = propagate.spectral_function(t, propagate.green_function(t, c, eps[0], 0.02), w, 0.05)
+    assert np.abs(a - a_ref).max() <= 1e-12 * np.abs(a_ref).max()
+    assert abs(qp - propagate.qp_peak(w, a_ref)) < 1e-10
+    assert amax == a.max()
+    with pytest.raises(rteom.RteomError):
+        P.spectral(w, -1.0)

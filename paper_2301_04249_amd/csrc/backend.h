@@ -30,7 +30,20 @@ struct GemmOp {
   // are summed in a fixed order by a second kernel.
   int splitk = 1;
   double* partial = nullptr;
+  // bf16x3 with pre-split operands: scratch of split_doubles(...) doubles that
+  // receives A and B as bf16 hi/lo planes ([batch][rows][k], k contiguous and
+  // zero padded to kSplitK) before the product; nullptr = split while staging.
+  double* split = nullptr;
 };
+
+// K granularity of pre-split planes, and the scratch (in doubles) they need.
+constexpr int64_t kSplitK = 32;
+inline int64_t split_ld(int64_t K) { return (K + kSplitK - 1) / kSplitK * kSplitK; }
+inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch, bool ac, bool bc) {
+  // ushort planes: hi and lo for each real plane of A ([M][ld]) and B ([N][ld])
+  const int64_t us = 2 * split_ld(K) * batch * (M * (ac ? 2 : 1) + N * (bc ? 2 : 1));
+  return (us + 3) / 4 + 64;   // 4 ushorts per double, +64 for alignment of the B planes
+}
 
 // out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an
 // nd-dimensional index space; strides per operand.  in may be real while out is

@@ -49,6 +49,11 @@ struct GemmArgs {
   int64_t kchunk;             // K elements per split (multiple of BK)
   double* pr; double* pi;     // partials [splitk][M][N]
   int m_fast;                 // logical tile order: row tiles fastest (B is the larger operand)
+  // pre-split bf16 planes (gemm_bf16x3_split): A planes [batch][M][sld], B planes
+  // [batch][N][sld] in the order re hi, re lo, im hi, im lo
+  const unsigned short* sa[4];
+  const unsigned short* sb[4];
+  int64_t sld;
 };
 
 // Output tile of work-group `bid`.  Work-groups are dispatched round-robin over
@@ -480,6 +485,180 @@ __global__ __launch_bounds__(256) void gemm_smallk(GemmArgs g, int n_inner) {
 }
 
 // C = alpha * sum_s P[s] + beta * C, summed in split order (deterministic).
+// ---------------------------------------------------------------------------
+// bf16 x 3 with operands split once before the product: split_kernel writes a
+// strided float64 plane as hi/lo bf16 planes [batch][rows][ld] (k contiguous,
+// zero padded from K to ld, ld a multiple of 32); gemm_bf16x3_split then stages
+// 16-byte chunks of those planes into LDS with no conversion work.  The split of
+// each element and the MFMA sequence per output element are those of
+// gemm_bf16x3, so both kernels give the same result.
+__global__ __launch_bounds__(256) void split_kernel(const double* src, int64_t rows, int64_t K, int64_t s_row,
+                                                    int64_t s_k, int64_t s_b, int64_t ld, unsigned short* hi,
+                                                    unsigned short* lo) {
+  __shared__ double tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64, b = blockIdx.z;
+  const double* S = src + b * s_b;
+  const int t = threadIdx.x;
+  const bool kfast = s_k == 1;    // read along the unit-stride index
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = t & 63, c = (t >> 6) + 4 * i;
+    const int rr = kfast ? c : a, kk = kfast ? a : c;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    tile[rr][kk] = (r < rows && k < K) ? S[r * s_row + k * s_k] : 0.0;
+  }
+  __syncthreads();
+  unsigned short* H = hi + b * rows * ld;
+  unsigned short* L = lo + b * rows * ld;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int kk = t & 63, rr = (t >> 6) + 4 * i;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    if (r < rows && k < ld) {
+      unsigned short h, l;
+      split_bf16(tile[rr][kk], h, l);
+      H[r * ld + k] = h;
+      L[r * ld + k] = l;
+    }
+  }
+}
+
+template <bool AC, bool BC, int WM, int WN>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_bf16x3_split(GemmArgs g) {
+  constexpr int TM = 32 * WM, TN = 32 * WN, LDK = BKH + PADH;
+  constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
+  constexpr int CA = TM / 64, CB = TN / 64;             // 16-byte chunks per thread and plane
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) unsigned short sa[2][PA][TM][LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short sb[2][PB][TN][LDK];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t tm, tn;
+  tile_coords(g, blockIdx.x, tm, tn);
+  const int64_t m0 = tm * TM, n0 = tn * TN;
+  const int crow = tid >> 2, cofs = (tid & 3) * 8;      // 64 rows x 4 chunks of 8 k per pass
+  int64_t kbeg = 0, kend = g.sld, b0 = blockIdx.y, bstep = gridDim.y;
+  if (g.splitk > 1) {
+    kbeg = (int64_t)blockIdx.y * g.kchunk;
+    kend = kbeg + g.kchunk < g.sld ? kbeg + g.kchunk : g.sld;
+    b0 = 0;
+    bstep = 1;
+  }
+  for (int64_t b = b0; b < g.batch; b += bstep) {
+    const int64_t ao = b * g.M * g.sld, bo = b * g.N * g.sld;
+    f4 accr[WM][WN], acci[WM][WN];
+#pragma unroll
+    for (int x = 0; x < WM; ++x)
+#pragma unroll
+      for (int y = 0; y < WN; ++y) {
+        accr[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+        acci[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+      }
+    u4 ra[PA][CA], rb[PB][CB];
+    auto fetch = [&](int64_t k0) {
+#pragma unroll
+      for (int c = 0; c < CA; ++c) {
+        const int64_t gm = m0 + crow + 64 * c;
+#pragma unroll
+        for (int p = 0; p < PA; ++p)
+          ra[p][c] = gm < g.M ? *reinterpret_cast<const u4*>(g.sa[p] + ao + gm * g.sld + k0 + cofs) : u4{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int c = 0; c < CB; ++c) {
+        const int64_t gn = n0 + crow + 64 * c;
+#pragma unroll
+        for (int p = 0; p < PB; ++p)
+          rb[p][c] = gn < g.N ? *reinterpret_cast<const u4*>(g.sb[p] + bo + gn * g.sld + k0 + cofs) : u4{0, 0, 0, 0};
+      }
+    };
+    auto stage = [&](int buf) {
+#pragma unroll
+      for (int c = 0; c < CA; ++c)
+#pragma unroll
+        for (int p = 0; p < PA; ++p) *reinterpret_cast<u4*>(&sa[buf][p][crow + 64 * c][cofs]) = ra[p][c];
+#pragma unroll
+      for (int c = 0; c < CB; ++c)
+#pragma unroll
+        for (int p = 0; p < PB; ++p) *reinterpret_cast<u4*>(&sb[buf][p][crow + 64 * c][cofs]) = rb[p][c];
+    };
+    if (kbeg < kend) {
+      fetch(kbeg);
+      stage(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    const int kk = (lane >> 4) * 8;
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BKH) {
+      const bool more = k0 + BKH < kend;
+      if (more) fetch(k0 + BKH);
+      bf8 xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
+#pragma unroll
+      for (int x = 0; x < WM; ++x) {
+        const int row = wm * 16 * WM + x * 16 + (lane & 15);
+        xrh[x] = ld8(&sa[buf][0][row][kk]);
+        xrl[x] = ld8(&sa[buf][1][row][kk]);
+        if (AC) { xih[x] = ld8(&sa[buf][2 % PA][row][kk]); xil[x] = ld8(&sa[buf][3 % PA][row][kk]); }
+      }
+#pragma unroll
+      for (int y = 0; y < WN; ++y) {
+        const int col = wn * 16 * WN + y * 16 + (lane & 15);
+        yrh[y] = ld8(&sb[buf][0][col][kk]);
+        yrl[y] = ld8(&sb[buf][1][col][kk]);
+        if (BC) { yih[y] = ld8(&sb[buf][2 % PB][col][kk]); yil[y] = ld8(&sb[buf][3 % PB][col][kk]); }
+      }
+#pragma unroll
+      for (int x = 0; x < WM; ++x)
+#pragma unroll
+        for (int y = 0; y < WN; ++y) {
+          accr[x][y] = mma3(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
+          if (AC && BC) {
+            accr[x][y] = mma3(neg8(xih[x]), neg8(xil[x]), yih[y], yil[y], accr[x][y]);
+            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+          } else if (AC) {
+            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+          } else if (BC) {
+            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+          }
+        }
+      if (more) stage(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+    const bool split = g.splitk > 1;
+    double* Cr = split ? g.pr + (int64_t)blockIdx.y * g.M * g.N : g.cr + b * g.csb;
+    double* Ci = (AC || BC) ? (split ? g.pi + (int64_t)blockIdx.y * g.M * g.N : g.ci + b * g.csb) : nullptr;
+    const int64_t sm = split ? g.N : g.csm, sn = split ? 1 : g.csn;
+#pragma unroll
+    for (int x = 0; x < WM; ++x)
+#pragma unroll
+      for (int y = 0; y < WN; ++y)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t gm = m0 + wm * 16 * WM + x * 16 + 4 * (lane >> 4) + r;
+          const int64_t gn = n0 + wn * 16 * WN + y * 16 + (lane & 15);
+          if (gm < g.M && gn < g.N) {
+            const int64_t o = gm * sm + gn * sn;
+            if (split) {
+              Cr[o] = (double)accr[x][y][r];
+              if (AC || BC) Ci[o] = (double)acci[x][y][r];
+            } else {
+              double vr = g.alpha * (double)accr[x][y][r];
+              if (g.beta) vr += Cr[o];
+              Cr[o] = vr;
+              if (AC || BC) {
+                double vi = g.alpha * (double)acci[x][y][r];
+                if (g.beta) vi += Ci[o];
+                Ci[o] = vi;
+              }
+            }
+          }
+        }
+  }
+}
+
 __global__ __launch_bounds__(256) void splitk_reduce(GemmArgs g, int cplx) {
   const int64_t total = g.M * g.N;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -851,6 +1030,35 @@ void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool 
   else gemm_bf16x3<AC, BC, false, false><<<grid, kThreads, 0, st>>>(g);
 }
 
+// Pre-split bf16x3 tile shapes: two LDS buffers of every hi/lo plane must fit
+// 80 KB so that two work-groups share a CU.
+constexpr int split_lds_bytes(bool ac, bool bc, int v) {
+  return 2 * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
+}
+inline bool split_tile_allowed(int v, bool ac, bool bc) {
+  return v >= 0 && v < kTiles && split_lds_bytes(ac, bc, v) <= 80 * 1024;
+}
+
+template <bool AC, bool BC, int WM, int WN, int V>
+void launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if constexpr (split_lds_bytes(AC, BC, V) <= 80 * 1024) gemm_bf16x3_split<AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
+}
+
+template <bool AC, bool BC>
+void launch_split(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if (v == 1) launch_split_tile<AC, BC, 2, 4, 1>(grid, st, g);
+  else if (v == 2) launch_split_tile<AC, BC, 4, 2, 2>(grid, st, g);
+  else if (v == 3) launch_split_tile<AC, BC, 4, 4, 3>(grid, st, g);
+  else launch_split_tile<AC, BC, 2, 2, 0>(grid, st, g);
+}
+
+void launch_split_gemm(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
+  if (ac && bc) launch_split<true, true>(v, grid, st, g);
+  else if (ac) launch_split<true, false>(v, grid, st, g);
+  else if (bc) launch_split<false, true>(v, grid, st, g);
+  else launch_split<false, false>(v, grid, st, g);
+}
+
 template <bool AC, bool BC>
 void launch_prec(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
   if (prec == 0) launch_mfma<double, AC, BC>(v, grid, st, g, akc, bkc);
@@ -992,18 +1200,48 @@ class HipBackend : public Backend {
     }
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
-    const int v = choose_tile(op, g, ac, bc, akc, bkc);
+    const bool presplit = op.prec == 2 && op.split != nullptr;
+    if (presplit) {
+      begin();
+      split_operands(op, g, ac, bc);
+      end();
+    }
+    const int v = choose_tile(op, g, ac, bc, akc, bkc, presplit);
     if (v < 0) return;
     dim3 grid;
     if (!shape_grid(g, v, op.batch, &grid)) return;
     begin();
-    launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
+    if (presplit) launch_split_gemm(v, grid, stream_, g, ac, bc);
+    else launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
     launched("gemm");
     if (g.splitk > 1) {
       splitk_reduce<<<grid_for(op.M * op.N), 256, 0, stream_>>>(g, cplx ? 1 : 0);
       launched("splitk_reduce");
     }
     end();
+  }
+
+  // bf16 hi/lo planes of A ([batch][M][ld]) and B ([batch][N][ld]) in op.split.
+  void split_operands(const GemmOp& op, GemmArgs& g, bool ac, bool bc) {
+    const int64_t ld = split_ld(op.K), asz = op.batch * op.M * ld, bsz = op.batch * op.N * ld;
+    unsigned short* base = reinterpret_cast<unsigned short*>(op.split);
+    const int pa = ac ? 4 : 2, pb = bc ? 4 : 2;
+    for (int p = 0; p < 4; ++p) {
+      g.sa[p] = p < pa ? base + p * asz : nullptr;
+      g.sb[p] = p < pb ? base + pa * asz + p * bsz : nullptr;
+    }
+    g.sld = ld;
+    auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, const unsigned short* h,
+                   const unsigned short* l) {
+      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)op.batch);
+      split_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, ld, const_cast<unsigned short*>(h),
+                                               const_cast<unsigned short*>(l));
+      launched("split");
+    };
+    run(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, g.sa[0], g.sa[1]);
+    if (ac) run(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, g.sa[2], g.sa[3]);
+    run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[0], g.sb[1]);
+    if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[2], g.sb[3]);
   }
 
   void set_tuning(int on) override { tuning_ = on != 0; }
@@ -1037,14 +1275,15 @@ class HipBackend : public Backend {
     return std::ceil(units / 256.0) * (tm * tn / 4096.0) / eff;
   }
 
-  int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc) {
-    if (force_ >= 0) return tile_allowed(force_, op.prec, ac, bc) ? force_ : 0;
+  int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc, bool presplit) {
+    auto allowed = [&](int v) { return presplit ? split_tile_allowed(v, ac, bc) : tile_allowed(v, op.prec, ac, bc); };
+    if (force_ >= 0) return allowed(force_) ? force_ : 0;
     int cand[kTiles], nc = 0;
     for (int v = 0; v < kTiles; ++v)
-      if (tile_allowed(v, op.prec, ac, bc)) cand[nc++] = v;
+      if (allowed(v)) cand[nc++] = v;
     if (nc == 1) return cand[0];
-    const std::array<int64_t, 10> key = {op.prec, op.M, op.N, op.K, op.batch, (int64_t)ac, (int64_t)bc,
-                                         (int64_t)akc, (int64_t)bkc, (int64_t)g.splitk};
+    const std::array<int64_t, 10> key = {op.prec + (presplit ? 8 : 0), op.M, op.N, op.K, op.batch, (int64_t)ac,
+                                         (int64_t)bc, (int64_t)akc, (int64_t)bkc, (int64_t)g.splitk};
     auto it = tuned_.find(key);
     if (it != tuned_.end()) return it->second;
     if (!tuning_ || capturing_) {
@@ -1072,7 +1311,8 @@ class HipBackend : public Backend {
         dim3 grid;
         if (!shape_grid(gt, cand[i], op.batch, &grid)) return -1;
         record(hipEventRecord(tune_a_, stream_), "hipEventRecord");
-        launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
+        if (presplit) launch_split_gemm(cand[i], grid, stream_, gt, ac, bc);
+        else launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
         launched("gemm (tuning)");
         record(hipEventRecord(tune_b_, stream_), "hipEventRecord");
         record(hipEventSynchronize(tune_b_), "hipEventSynchronize");

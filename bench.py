@@ -45,10 +45,10 @@ PEAK_HBM_GBS = 8000.0
 WORKLOADS = {
     "formaldehyde": dict(shape=FORMALDEHYDE, cfg=1, dt=0.025, passes=3, steps=4,
                          desc="formaldehyde-shaped core hole: o=8, v=110 per spin, Q=600, beta hole, dt=0.025 au"),
-    "batched": dict(batch=16, cfg=2, dt=0.025, passes=2, steps=10, cpu_sample="formaldehyde",
+    "batched": dict(batch=16, cfg=2, dt=0.025, passes=2, fp_map=1, steps=10, cpu_sample="formaldehyde",
                     desc="16 independent core holes of uneven shape (o in [5,20], v in [40,200] per spin, "
-                         "Q = 4 v, L scaled by (16/v)^(1/2), beta holes), one graph launch per time step for "
-                         "all, dt=0.025 au"),
+                         "Q = 4 v, L scaled by (16/v)^(1/2), beta holes), diagonal fixed-point map, one graph "
+                         "launch per time step for all, dt=0.025 au"),
     "tiny": dict(shape=TINY, cfg=0, dt=0.025, passes=3, steps=4,
                  desc="tiny: o=4, v=16 per spin, Q=48, beta hole, dt=0.025 au"),
     # the paper's ESCA run: 71 occupied / 649 virtual spin-orbitals in total
@@ -102,7 +102,8 @@ def run_batch(args, work):
         out = []
         for sh, (eps, chol) in zip(shapes, systems):
             out.append(rteom.Propagator(eps, chol, sh.o, sh.o, 0, 1, prec=args.prec, fixed_iters=passes,
-                                        workspace="torch", max_steps=args.steps + args.warmup + 4, graph=graph))
+                                        fp_map=work.get("fp_map", 0), workspace="torch",
+                                        max_steps=args.steps + args.warmup + 4, graph=graph))
         return out
 
     ps = props(True)

@@ -1201,16 +1201,12 @@ class HipBackend : public Backend {
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
     const bool presplit = op.prec == 2 && op.split != nullptr;
-    if (presplit) {
-      begin();
-      split_operands(op, g, ac, bc);
-      end();
-    }
+    begin();   // one timed operation: operand split, product and split-K reduction
+    if (presplit) split_operands(op, g, ac, bc);
     const int v = choose_tile(op, g, ac, bc, akc, bkc, presplit);
-    if (v < 0) return;
+    if (v < 0) { end(); return; }
     dim3 grid;
-    if (!shape_grid(g, v, op.batch, &grid)) return;
-    begin();
+    if (!shape_grid(g, v, op.batch, &grid)) { end(); return; }
     if (presplit) launch_split_gemm(v, grid, stream_, g, ac, bc);
     else launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
     launched("gemm");

@@ -30,19 +30,21 @@ struct GemmOp {
   // are summed in a fixed order by a second kernel.
   int splitk = 1;
   double* partial = nullptr;
-  // bf16x3 with pre-split operands: scratch of split_doubles(...) doubles that
-  // receives A and B as bf16 hi/lo planes ([batch][rows][k], k contiguous and
-  // zero padded to kSplitK) before the product; nullptr = split while staging.
+  // Operands converted once before the product (reduced precisions): scratch of
+  // split_doubles(...) doubles that receives A and B in the contraction's storage
+  // ([batch][rows][k], k contiguous, zero padded to kSplitK): bf16 hi/lo planes
+  // for bf16x3, float planes for fp32.  nullptr = convert while staging.
   double* split = nullptr;
 };
 
-// K granularity of pre-split planes, and the scratch (in doubles) they need.
+// K granularity of converted planes, and the scratch (in doubles) they need.
 constexpr int64_t kSplitK = 32;
 inline int64_t split_ld(int64_t K) { return (K + kSplitK - 1) / kSplitK * kSplitK; }
-inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch, bool ac, bool bc) {
-  // ushort planes: hi and lo for each real plane of A ([M][ld]) and B ([N][ld])
-  const int64_t us = 2 * split_ld(K) * batch * (M * (ac ? 2 : 1) + N * (bc ? 2 : 1));
-  return (us + 3) / 4 + 64;   // 4 ushorts per double, +64 for alignment of the B planes
+inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch, bool ac, bool bc, int prec) {
+  // elements of all real planes of A ([M][ld]) and B ([N][ld])
+  const int64_t el = split_ld(K) * batch * (M * (ac ? 2 : 1) + N * (bc ? 2 : 1));
+  // bf16x3: two 2-byte planes per real plane; fp32: one 4-byte plane; +64 for alignment
+  return (prec == 2 ? (2 * el + 3) / 4 : (el + 1) / 2) + 64;
 }
 
 // out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an

@@ -103,7 +103,10 @@ template <> struct Mfma<float> {
 // holding WM x WN accumulator blocks of 16 x 16.  Wider tiles stage fewer
 // operand bytes per MFMA; the complex x complex product already has four MFMAs
 // per staged fragment pair and keeps 64 x 64.
-template <typename T, bool AC, bool BC, bool AKC, bool BKC, int WM, int WN>
+// S is the operand storage type: double, or float for operands converted to
+// float planes before the product (their pointers travel in the double fields of
+// GemmArgs and their strides count floats).
+template <typename T, typename S, bool AC, bool BC, bool AKC, bool BKC, int WM, int WN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_mfma(GemmArgs g) {
   typedef typename Mfma<T>::acc_t acc_t;
   constexpr int TM = 32 * WM, TN = 32 * WN;
@@ -147,10 +150,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
   const int64_t a_off = (m0 + am0) * g.asm_ + ak0 * g.ask, b_off = (n0 + bn0) * g.bsn + bk0 * g.bsk;
   const int64_t a_mrem = g.M - m0 - am0, b_nrem = g.N - n0 - bn0;   // rows / columns left
   for (int64_t b = b0; b < g.batch; b += bstep) {
-    const double* Ar = g.ar + b * g.asb;
-    const double* Ai = AC ? g.ai + b * g.asb : nullptr;
-    const double* Br = g.br + b * g.bsb;
-    const double* Bi = BC ? g.bi + b * g.bsb : nullptr;
+    const S* Ar = reinterpret_cast<const S*>(g.ar) + b * g.asb;
+    const S* Ai = AC ? reinterpret_cast<const S*>(g.ai) + b * g.asb : nullptr;
+    const S* Br = reinterpret_cast<const S*>(g.br) + b * g.bsb;
+    const S* Bi = BC ? reinterpret_cast<const S*>(g.bi) + b * g.bsb : nullptr;
     acc_t accr[WM][WN], acci[WM][WN];
 #pragma unroll
     for (int x = 0; x < WM; ++x)
@@ -159,13 +162,13 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
         accr[x][y] = acc_t{0, 0, 0, 0};
         acci[x][y] = acc_t{0, 0, 0, 0};
       }
-    double pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
+    S pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
     auto fetch = [&](int64_t k0) {
       const int64_t ka = kend - k0 - ak0, kb = kend - k0 - bk0;   // k positions left
 #pragma unroll
       for (int r = 0; r < NA; ++r) {
-        pa_r[r] = 0.0;
-        pa_i[r] = 0.0;
+        pa_r[r] = 0;
+        pa_i[r] = 0;
         if (r * AMS < a_mrem && r * AKS < ka) {
           const int64_t o = a_off + k0 * g.ask + r * a_rs;
           pa_r[r] = Ar[o];
@@ -174,8 +177,8 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
       }
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
-        pb_r[r] = 0.0;
-        pb_i[r] = 0.0;
+        pb_r[r] = 0;
+        pb_i[r] = 0;
         if (r * BNS < b_nrem && r * BKS < kb) {
           const int64_t o = b_off + k0 * g.bsk + r * b_rs;
           pb_r[r] = Br[o];
@@ -520,6 +523,31 @@ __global__ __launch_bounds__(256) void split_kernel(const double* src, int64_t r
       H[r * ld + k] = h;
       L[r * ld + k] = l;
     }
+  }
+}
+
+// The float counterpart: a strided float64 plane as float [batch][rows][ld].
+__global__ __launch_bounds__(256) void f32_kernel(const double* src, int64_t rows, int64_t K, int64_t s_row,
+                                                  int64_t s_k, int64_t s_b, int64_t ld, float* dst) {
+  __shared__ double tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64, b = blockIdx.z;
+  const double* S = src + b * s_b;
+  const int t = threadIdx.x;
+  const bool kfast = s_k == 1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = t & 63, c = (t >> 6) + 4 * i;
+    const int rr = kfast ? c : a, kk = kfast ? a : c;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    tile[rr][kk] = (r < rows && k < K) ? S[r * s_row + k * s_k] : 0.0;
+  }
+  __syncthreads();
+  float* D = dst + b * rows * ld;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int kk = t & 63, rr = (t >> 6) + 4 * i;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    if (r < rows && k < ld) D[r * ld + k] = (float)tile[rr][kk];
   }
 }
 
@@ -995,11 +1023,32 @@ inline bool tile_allowed(int v, int prec, bool ac, bool bc) {
 
 template <typename T, bool AC, bool BC, int WM, int WN>
 void launch_mfma_tile(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if (akc && bkc) gemm_mfma<T, AC, BC, true, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else if (akc) gemm_mfma<T, AC, BC, true, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else if (bkc) gemm_mfma<T, AC, BC, false, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else gemm_mfma<T, AC, BC, false, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  if (akc && bkc) gemm_mfma<T, double, AC, BC, true, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else if (akc) gemm_mfma<T, double, AC, BC, true, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else if (bkc) gemm_mfma<T, double, AC, BC, false, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  else gemm_mfma<T, double, AC, BC, false, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
 }
+
+// float operands converted before the product: both k-contiguous
+template <bool AC, bool BC>
+void launch_f32_converted(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if constexpr (AC && BC) {
+    gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
+  } else if constexpr (AC) {
+    if (v == 1) gemm_mfma<float, float, AC, BC, true, true, 2, 4><<<grid, kThreads, 0, st>>>(g);
+    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
+  } else if constexpr (BC) {
+    if (v == 2) gemm_mfma<float, float, AC, BC, true, true, 4, 2><<<grid, kThreads, 0, st>>>(g);
+    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
+  } else {
+    if (v == 1) gemm_mfma<float, float, AC, BC, true, true, 2, 4><<<grid, kThreads, 0, st>>>(g);
+    else if (v == 2) gemm_mfma<float, float, AC, BC, true, true, 4, 2><<<grid, kThreads, 0, st>>>(g);
+    else if (v == 3) gemm_mfma<float, float, AC, BC, true, true, 4, 4><<<grid, kThreads, 0, st>>>(g);
+    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
+  }
+}
+
+void launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc);
 
 template <typename T, bool AC, bool BC>
 void launch_mfma(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
@@ -1057,6 +1106,20 @@ void launch_split_gemm(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool
   else if (ac) launch_split<true, false>(v, grid, st, g);
   else if (bc) launch_split<false, true>(v, grid, st, g);
   else launch_split<false, false>(v, grid, st, g);
+}
+
+void launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
+  if (prec == 2) {
+    launch_split_gemm(v, grid, st, g, ac, bc);
+  } else if (ac && bc) {
+    launch_f32_converted<true, true>(v, grid, st, g);
+  } else if (ac) {
+    launch_f32_converted<true, false>(v, grid, st, g);
+  } else if (bc) {
+    launch_f32_converted<false, true>(v, grid, st, g);
+  } else {
+    launch_f32_converted<false, false>(v, grid, st, g);
+  }
 }
 
 template <bool AC, bool BC>
@@ -1200,14 +1263,17 @@ class HipBackend : public Backend {
     }
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
-    const bool presplit = op.prec == 2 && op.split != nullptr;
-    begin();   // one timed operation: operand split, product and split-K reduction
-    if (presplit) split_operands(op, g, ac, bc);
+    const bool presplit = op.prec != 0 && op.split != nullptr;
+    begin();   // one timed operation: operand conversion, product and split-K reduction
+    if (presplit) {
+      if (op.prec == 2) split_operands(op, g, ac, bc);
+      else f32_operands(op, g, ac, bc);
+    }
     const int v = choose_tile(op, g, ac, bc, akc, bkc, presplit);
     if (v < 0) { end(); return; }
     dim3 grid;
     if (!shape_grid(g, v, op.batch, &grid)) { end(); return; }
-    if (presplit) launch_split_gemm(v, grid, stream_, g, ac, bc);
+    if (presplit) launch_converted_gemm(op.prec, v, grid, stream_, g, ac, bc);
     else launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
     launched("gemm");
     if (g.splitk > 1) {
@@ -1238,6 +1304,30 @@ class HipBackend : public Backend {
     if (ac) run(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, g.sa[2], g.sa[3]);
     run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[0], g.sb[1]);
     if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[2], g.sb[3]);
+  }
+
+  // float planes of A ([batch][M][ld]) and B ([batch][N][ld]) in op.split; the
+  // product then reads them through the double fields of g with float strides.
+  void f32_operands(const GemmOp& op, GemmArgs& g, bool ac, bool bc) {
+    const int64_t ld = split_ld(op.K), asz = op.batch * op.M * ld, bsz = op.batch * op.N * ld;
+    float* base = reinterpret_cast<float*>(op.split);
+    float* pl[4] = {base, ac ? base + asz : nullptr, base + (ac ? 2 : 1) * asz, nullptr};
+    pl[3] = bc ? pl[2] + bsz : nullptr;
+    auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, float* d) {
+      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)op.batch);
+      f32_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, ld, d);
+      launched("f32 convert");
+    };
+    run(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, pl[0]);
+    if (ac) run(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, pl[1]);
+    run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, pl[2]);
+    if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, pl[3]);
+    g.ar = reinterpret_cast<const double*>(pl[0]);
+    g.ai = reinterpret_cast<const double*>(pl[1]);
+    g.br = reinterpret_cast<const double*>(pl[2]);
+    g.bi = reinterpret_cast<const double*>(pl[3]);
+    g.asm_ = ld; g.ask = 1; g.asb = op.M * ld;
+    g.bsn = ld; g.bsk = 1; g.bsb = op.N * ld;
   }
 
   void set_tuning(int on) override { tuning_ = on != 0; }
@@ -1272,7 +1362,9 @@ class HipBackend : public Backend {
   }
 
   int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc, bool presplit) {
-    auto allowed = [&](int v) { return presplit ? split_tile_allowed(v, ac, bc) : tile_allowed(v, op.prec, ac, bc); };
+    auto allowed = [&](int v) {
+      return (presplit && op.prec == 2) ? split_tile_allowed(v, ac, bc) : tile_allowed(v, op.prec, ac, bc);
+    };
     if (force_ >= 0) return allowed(force_) ? force_ : 0;
     int cand[kTiles], nc = 0;
     for (int v = 0; v < kTiles; ++v)
@@ -1307,7 +1399,7 @@ class HipBackend : public Backend {
         dim3 grid;
         if (!shape_grid(gt, cand[i], op.batch, &grid)) return -1;
         record(hipEventRecord(tune_a_, stream_), "hipEventRecord");
-        if (presplit) launch_split_gemm(cand[i], grid, stream_, gt, ac, bc);
+        if (presplit) launch_converted_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc);
         else launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
         launched("gemm (tuning)");
         record(hipEventRecord(tune_b_, stream_), "hipEventRecord");

@@ -11,7 +11,7 @@ namespace {
 constexpr int64_t kComputeUnits = 256;   // MI355X
 constexpr int64_t kMinSplitK = 128;      // shortest K chunk worth a work-group
 constexpr int64_t kSmallK = 16;          // sums this short run on the vector units
-constexpr int64_t kSplitMinK = 64;       // bf16x3: shortest sum whose operands are split once
+constexpr int64_t kSplitMinK = 64;       // reduced precision: shortest sum whose operands are converted once
 constexpr double kSplitMinMacs = 1e9;    // ... and smallest product (MACs) worth the extra pass
 }  // namespace
 
@@ -358,11 +358,12 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
       op.partial = scratch->take((cplx_out ? 2 : 1) * best_s * op.M * op.N);
     }
   }
-  // bf16x3: large products split their operands into bf16 hi/lo planes once,
-  // instead of in every work-group that stages them
-  if (prec == 2 && op.K >= kSplitMinK && static_cast<double>(op.M) * op.N * op.K * op.batch >= kSplitMinMacs &&
+  // Reduced precisions: large products convert their operands once (bf16 hi/lo
+  // planes, or float planes) instead of in every work-group that stages them
+  if (prec != 0 && op.K >= kSplitMinK && static_cast<double>(op.M) * op.N * op.K * op.batch >= kSplitMinMacs &&
       op.M >= 64 && op.N >= 64)
-    op.split = scratch->take(split_doubles(op.M, op.N, op.K, op.batch, op.a_im != nullptr, op.b_im != nullptr));
+    op.split = scratch->take(
+        split_doubles(op.M, op.N, op.K, op.batch, op.a_im != nullptr, op.b_im != nullptr, prec));
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
 #ifdef RTEOM_PLAN_TRACE

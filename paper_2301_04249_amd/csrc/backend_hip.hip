@@ -207,6 +207,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
       const bool more = k0 + BK < kend;
       if (more) fetch(k0 + BK);
+      // float64: the wave multiplying runs at raised priority, so that its MFMA
+      // chain is not held up by the other wave on the SIMD staging its next tile
+      if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
       // Wide tiles keep fragments of one (float64) or two (float32) k-steps in
       // flight instead of four: the accumulators fill most of the register file.
 #pragma unroll (WM * WN <= 4 ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
@@ -241,6 +244,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
             }
           }
       }
+      if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(0);
       if (more) stage(buf ^ 1);
       __syncthreads();
       buf ^= 1;

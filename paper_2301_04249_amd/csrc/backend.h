@@ -32,7 +32,8 @@ struct GemmOp {
   double* partial = nullptr;
   // Operands converted once before the product (reduced precisions): scratch of
   // split_doubles(...) doubles that receives A and B in the contraction's storage
-  // ([batch][rows][k], k contiguous, zero padded to kSplitK): bf16 hi/lo planes
+  // ([batch][rows][k], k contiguous, zero padded to kSplitK; one matrix when the
+  // operand's batch stride is 0): bf16 hi/lo planes
   // for bf16x3, float planes for fp32.  nullptr = convert while staging.
   double* split = nullptr;
 };
@@ -40,9 +41,11 @@ struct GemmOp {
 // K granularity of converted planes, and the scratch (in doubles) they need.
 constexpr int64_t kSplitK = 32;
 inline int64_t split_ld(int64_t K) { return (K + kSplitK - 1) / kSplitK * kSplitK; }
-inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch, bool ac, bool bc, int prec) {
+// batch_a / batch_b: matrices of each operand (1 when it is the same for every batch entry)
+inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch_a, int64_t batch_b, bool ac, bool bc,
+                             int prec) {
   // elements of all real planes of A ([M][ld]) and B ([N][ld])
-  const int64_t el = split_ld(K) * batch * (M * (ac ? 2 : 1) + N * (bc ? 2 : 1));
+  const int64_t el = split_ld(K) * (batch_a * M * (ac ? 2 : 1) + batch_b * N * (bc ? 2 : 1));
   // bf16x3: two 2-byte planes per real plane; fp32: one 4-byte plane; +64 for alignment
   return (prec == 2 ? (2 * el + 3) / 4 : (el + 1) / 2) + 64;
 }

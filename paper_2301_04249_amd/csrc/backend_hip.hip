@@ -53,7 +53,7 @@ struct GemmArgs {
   // [batch][N][sld] in the order re hi, re lo, im hi, im lo
   const unsigned short* sa[4];
   const unsigned short* sb[4];
-  int64_t sld;
+  int64_t sld, sab, sbb;      // row length and batch strides (0: one matrix for all batch entries)
 };
 
 // Output tile of work-group `bid`.  Work-groups are dispatched round-robin over
@@ -579,7 +579,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     bstep = 1;
   }
   for (int64_t b = b0; b < g.batch; b += bstep) {
-    const int64_t ao = b * g.M * g.sld, bo = b * g.N * g.sld;
+    const int64_t ao = b * g.sab, bo = b * g.sbb;
     f4 accr[WM][WN], acci[WM][WN];
 #pragma unroll
     for (int x = 0; x < WM; ++x)
@@ -748,6 +748,63 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
     }
     p.orr[oo] = vr;
     if (p.oi) p.oi[oo] = vi;
+  }
+}
+
+// The same operation when the input's and the output's unit-stride dimensions
+// differ (a transpose): 32 x 32 tiles of (din, dout) pass through LDS so that both
+// the reads (along din) and the writes (along dout) are coalesced.  The value of
+// every element is computed exactly as in permute_kernel (same scale order).
+__global__ __launch_bounds__(256) void permute_tiled(PermArgs p, int din, int dout, int64_t tiles_i,
+                                                     int64_t tiles_o, int64_t nblocks) {
+  __shared__ double tr[32][33], ti[32][33];
+  const int64_t ni = p.dim[din], no = p.dim[dout], ntile = tiles_i * tiles_o;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int64_t w = blockIdx.x; w < nblocks; w += gridDim.x) {
+    const int64_t tile = w % ntile;
+    int64_t rest = w / ntile;
+    const int64_t a0 = (tile % tiles_i) * 32, b0 = (tile / tiles_i) * 32;
+    int64_t x[kMaxDims];
+    int64_t io = 0, oo = 0;
+    for (int d = p.nd - 1; d >= 0; --d) {
+      if (d == din || d == dout) { x[d] = 0; continue; }
+      x[d] = rest % p.dim[d];
+      rest /= p.dim[d];
+      io += x[d] * p.istr[d];
+      oo += x[d] * p.ostr[d];
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t a = a0 + tx, c = b0 + ty + 8 * j;
+      double vr = 0.0, vi = 0.0;
+      if (a < ni && c < no) {
+        double sv = 1.0;
+        for (int d = p.nd - 1; d >= 0; --d)
+          if (p.sc[d]) sv *= p.sc[d][d == din ? a : (d == dout ? c : x[d])];
+        const int64_t o = io + a * p.istr[din] + c * p.istr[dout];
+        const double xr = p.ir[o], xi = p.ii ? p.ii[o] : 0.0;
+        vr = sv * (p.ar * xr - p.ai * xi);
+        vi = sv * (p.ar * xi + p.ai * xr);
+      }
+      tr[ty + 8 * j][tx] = vr;
+      ti[ty + 8 * j][tx] = vi;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t c = b0 + tx, a = a0 + ty + 8 * j;
+      if (a < ni && c < no) {
+        const int64_t o = oo + a * p.ostr[din] + c * p.ostr[dout];
+        double vr = tr[tx][ty + 8 * j], vi = ti[tx][ty + 8 * j];
+        if (p.beta) {
+          vr += p.orr[o];
+          if (p.oi) vi += p.oi[o];
+        }
+        p.orr[o] = vr;
+        if (p.oi) p.oi[o] = vi;
+      }
+    }
+    __syncthreads();
   }
 }
 
@@ -1289,7 +1346,8 @@ class HipBackend : public Backend {
 
   // bf16 hi/lo planes of A ([batch][M][ld]) and B ([batch][N][ld]) in op.split.
   void split_operands(const GemmOp& op, GemmArgs& g, bool ac, bool bc) {
-    const int64_t ld = split_ld(op.K), asz = op.batch * op.M * ld, bsz = op.batch * op.N * ld;
+    const int64_t ld = split_ld(op.K), nba = op.a_sb ? op.batch : 1, nbb = op.b_sb ? op.batch : 1;
+    const int64_t asz = nba * op.M * ld, bsz = nbb * op.N * ld;
     unsigned short* base = reinterpret_cast<unsigned short*>(op.split);
     const int pa = ac ? 4 : 2, pb = bc ? 4 : 2;
     for (int p = 0; p < 4; ++p) {
@@ -1297,9 +1355,11 @@ class HipBackend : public Backend {
       g.sb[p] = p < pb ? base + pa * asz + p * bsz : nullptr;
     }
     g.sld = ld;
+    g.sab = op.a_sb ? op.M * ld : 0;
+    g.sbb = op.b_sb ? op.N * ld : 0;
     auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, const unsigned short* h,
                    const unsigned short* l) {
-      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)op.batch);
+      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
       split_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, ld, const_cast<unsigned short*>(h),
                                                const_cast<unsigned short*>(l));
       launched("split");
@@ -1313,12 +1373,13 @@ class HipBackend : public Backend {
   // float planes of A ([batch][M][ld]) and B ([batch][N][ld]) in op.split; the
   // product then reads them through the double fields of g with float strides.
   void f32_operands(const GemmOp& op, GemmArgs& g, bool ac, bool bc) {
-    const int64_t ld = split_ld(op.K), asz = op.batch * op.M * ld, bsz = op.batch * op.N * ld;
+    const int64_t ld = split_ld(op.K), nba = op.a_sb ? op.batch : 1, nbb = op.b_sb ? op.batch : 1;
+    const int64_t asz = nba * op.M * ld, bsz = nbb * op.N * ld;
     float* base = reinterpret_cast<float*>(op.split);
     float* pl[4] = {base, ac ? base + asz : nullptr, base + (ac ? 2 : 1) * asz, nullptr};
     pl[3] = bc ? pl[2] + bsz : nullptr;
     auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, float* d) {
-      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)op.batch);
+      dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
       f32_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, ld, d);
       launched("f32 convert");
     };
@@ -1330,8 +1391,8 @@ class HipBackend : public Backend {
     g.ai = reinterpret_cast<const double*>(pl[1]);
     g.br = reinterpret_cast<const double*>(pl[2]);
     g.bi = reinterpret_cast<const double*>(pl[3]);
-    g.asm_ = ld; g.ask = 1; g.asb = op.M * ld;
-    g.bsn = ld; g.bsk = 1; g.bsb = op.N * ld;
+    g.asm_ = ld; g.ask = 1; g.asb = op.a_sb ? op.M * ld : 0;
+    g.bsn = ld; g.bsk = 1; g.bsb = op.b_sb ? op.N * ld : 0;
   }
 
   void set_tuning(int on) override { tuning_ = on != 0; }
@@ -1437,9 +1498,22 @@ class HipBackend : public Backend {
     if (p.total == 0) return;
     p.ir = op.in_re; p.ii = op.in_im; p.orr = op.out_re; p.oi = op.out_im;
     p.ar = op.alpha_re; p.ai = op.alpha_im; p.beta = op.beta;
+    // unit-stride dimension of each side (the innermost one if several)
+    int din = -1, dout = -1;
+    for (int d = 0; d < op.nd; ++d) {
+      if (op.dim[d] > 1 && op.in_str[d] == 1) din = d;
+      if (op.dim[d] > 1 && op.out_str[d] == 1) dout = d;
+    }
     begin();
-    permute_kernel<<<grid_for(p.total), 256, 0, stream_>>>(p);
-    launched("permute");
+    if (din >= 0 && dout >= 0 && din != dout && op.dim[din] >= 8 && op.dim[dout] >= 8 && op.in_re != op.out_re) {
+      const int64_t ti = (op.dim[din] + 31) / 32, to = (op.dim[dout] + 31) / 32;
+      const int64_t nblocks = p.total / (op.dim[din] * op.dim[dout]) * ti * to;
+      permute_tiled<<<(unsigned)std::min<int64_t>(nblocks, 1 << 18), 256, 0, stream_>>>(p, din, dout, ti, to, nblocks);
+      launched("permute (tiled)");
+    } else {
+      permute_kernel<<<grid_for(p.total), 256, 0, stream_>>>(p);
+      launched("permute");
+    }
     end();
   }
 

@@ -362,8 +362,8 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   // planes, or float planes) instead of in every work-group that stages them
   if (prec != 0 && op.K >= kSplitMinK && static_cast<double>(op.M) * op.N * op.K * op.batch >= kSplitMinMacs &&
       op.M >= 64 && op.N >= 64)
-    op.split = scratch->take(
-        split_doubles(op.M, op.N, op.K, op.batch, op.a_im != nullptr, op.b_im != nullptr, prec));
+    op.split = scratch->take(split_doubles(op.M, op.N, op.K, op.a_sb ? op.batch : 1, op.b_sb ? op.batch : 1,
+                                           op.a_im != nullptr, op.b_im != nullptr, prec));
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
 #ifdef RTEOM_PLAN_TRACE

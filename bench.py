@@ -30,10 +30,7 @@ KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float>", "bf16x3"
 # scaled by the same counters read on a plain device copy of known size; the
 # summaries (with the commands) are under profiles/.  Only workloads whose
 # ladder kernel has been counted since its last change are listed.
-TRAFFIC = {
-    # profiles/gemm_mfma_ladder_esca_fp64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0
-    ("esca", "fp64"): 1.0151e13,
-}
+TRAFFIC = {}
 
 DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",
          "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}

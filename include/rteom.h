@@ -111,7 +111,9 @@ rteom_status rteom_init(rteom_ctx** ctx, int32_t n_orb, int32_t n_occ_a, int32_t
 
 /* Advance n_steps time steps of length dt (Eq. trapzrule with fixed-point passes) and
    append C(t) for each.  micro_iters_out (nullable, host [n_steps]) receives the passes
-   used per step.  NOCONV leaves the amplitudes and C(t) at the last committed step. */
+   used per step.  NOCONV (or NONFINITE) leaves C(t) at the last committed step, the
+   amplitudes at the last iterate, and the context in a failed state (STATE) until
+   amplitudes are set or a checkpoint is restored. */
 rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* micro_iters_out);
 
 /* Copy the cumulant history to host: t_out [cap] times, c_out [cap][2] (re, im) of
@@ -119,6 +121,22 @@ rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* mic
    cap = 0 is a length query: nothing is written and *n_out = steps taken + 1. */
 rteom_status rteom_cumulant(const rteom_ctx* ctx, int64_t cap, double* t_out, double* c_out,
                             int64_t* n_out);
+
+/* Checkpoint and restart of a propagation (Sec. 3: runs of hundreds of atomic time units
+   need restarts).  The image holds the amplitudes T(t_n), the C(t) and E(t) histories and
+   the time grid t_0..t_n, behind a header (magic, version, n_orb, n_occ_a, n_occ_b,
+   n_chol, core_orb, core_spin, steps); integrals are not stored, the caller re-creates
+   the context from its inputs.  rteom_checkpoint: buf NULL -> *bytes = image size, OK;
+   cap < size -> *bytes = size, ARG; else the image is written to host buf.  STATE if the
+   context is in a failed state.  Synchronises the stream. */
+rteom_status rteom_checkpoint(rteom_ctx* ctx, void* buf, size_t cap, size_t* bytes);
+
+/* Restore an image written by rteom_checkpoint (host buf of len bytes) into a context
+   created with the same sizes and core orbital: amplitudes, histories and step count
+   are replaced and a failed state is cleared; options (precision, map, graph) are the
+   context's own.  ARG for a truncated or foreign image, mismatched sizes, or more steps
+   than the context's max_steps. */
+rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len);
 
 /* Spectral function of the core hole from the device C(t) history (Sec. 2.2: the
    cumulant form of the core Green's function, Eqs. cum_gf and cum_gf2):

@@ -855,6 +855,82 @@ rteom_status rteom_cumulant(const rteom_ctx* cctx, int64_t cap, double* t_out, d
   });
 }
 
+namespace {
+constexpr uint64_t kImageMagic = 0x4d4f4554522d5452ull;   // "RT-RTEOM" little-endian
+constexpr uint32_t kImageVersion = 1;
+struct ImageHeader {
+  uint64_t magic;
+  uint32_t version, reserved;
+  int32_t n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin;
+  int64_t nsteps, amp_doubles;
+};
+size_t image_bytes(int64_t nsteps, int64_t amp_doubles) {
+  // times, C history, E history, planar amplitudes
+  return sizeof(ImageHeader) + sizeof(double) * (size_t)((nsteps + 1) * 5 + amp_doubles);
+}
+}  // namespace
+
+rteom_status rteom_checkpoint(rteom_ctx* ctx, void* buf, size_t cap, size_t* bytes) {
+  if (!ctx || !bytes) { g_last_error = "NULL argument"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  if (c.failed) { c.err = "context is in a failed state"; return RTEOM_ERR_STATE; }
+  const int64_t amp = 2 * c.lay.size();
+  *bytes = image_bytes(c.nsteps, amp);
+  if (!buf) return RTEOM_OK;
+  if (cap < *bytes) { c.err = "checkpoint buffer too small"; return RTEOM_ERR_ARG; }
+  return guarded(ctx, [&] {
+    ImageHeader h{};
+    h.magic = kImageMagic;
+    h.version = kImageVersion;
+    h.n_orb = c.n; h.n_occ_a = c.na; h.n_occ_b = c.nb; h.n_chol = c.nq;
+    h.core_orb = c.core_orb; h.core_spin = c.core_spin;
+    h.nsteps = c.nsteps;
+    h.amp_doubles = amp;
+    char* p = static_cast<char*>(buf);
+    std::memcpy(p, &h, sizeof(h));
+    double* d = reinterpret_cast<double*>(p + sizeof(h));
+    const int64_t n = c.nsteps + 1;
+    for (int64_t k = 0; k < n; ++k) d[k] = c.times[k];
+    c.be->d2h(d + n, c.c_hist, sizeof(double) * 2 * n);
+    c.be->d2h(d + 3 * n, c.e_hist, sizeof(double) * 2 * n);
+    c.be->d2h(d + 5 * n, c.X, sizeof(double) * amp);
+  });
+}
+
+rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len) {
+  if (!ctx || !buf) { g_last_error = "NULL argument"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  ImageHeader h{};
+  if (len < sizeof(h)) { c.err = "checkpoint image truncated"; return RTEOM_ERR_ARG; }
+  std::memcpy(&h, buf, sizeof(h));
+  const int64_t amp = 2 * c.lay.size();
+  if (h.magic != kImageMagic || h.version != kImageVersion) { c.err = "not a checkpoint image"; return RTEOM_ERR_ARG; }
+  if (h.n_orb != c.n || h.n_occ_a != c.na || h.n_occ_b != c.nb || h.n_chol != c.nq || h.core_orb != c.core_orb ||
+      h.core_spin != c.core_spin || h.amp_doubles != amp) {
+    c.err = "checkpoint image is for another system";
+    return RTEOM_ERR_ARG;
+  }
+  if (h.nsteps < 0 || h.nsteps > c.opt.max_steps) { c.err = "checkpoint has more steps than max_steps"; return RTEOM_ERR_ARG; }
+  if (len < image_bytes(h.nsteps, amp)) { c.err = "checkpoint image truncated"; return RTEOM_ERR_ARG; }
+  const double* d = reinterpret_cast<const double*>(static_cast<const char*>(buf) + sizeof(h));
+  const int64_t n = h.nsteps + 1;
+  for (int64_t k = 0; k < 2 * n; ++k)
+    if (!std::isfinite(d[n + k]) || !std::isfinite(d[3 * n + k])) { c.err = "non-finite history"; return RTEOM_ERR_NONFINITE; }
+  for (int64_t k = 0; k < amp; ++k)
+    if (!std::isfinite(d[5 * n + k])) { c.err = "non-finite amplitude"; return RTEOM_ERR_NONFINITE; }
+  return guarded(ctx, [&] {
+    c.be->h2d(c.c_hist, d + n, sizeof(double) * 2 * n);
+    c.be->h2d(c.e_hist, d + 3 * n, sizeof(double) * 2 * n);
+    c.be->h2d(c.X, d + 5 * n, sizeof(double) * amp);
+    const int64_t step = h.nsteps;
+    c.be->h2d(c.dstep, &step, sizeof(step));
+    c.nsteps = h.nsteps;
+    c.times.assign(d, d + n);
+    c.failed = false;
+    c.be->sync();
+  });
+}
+
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out) {
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }

@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # every exported symbol of include/rteom.h
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
-    "rteom_spectral", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_spectral", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
     "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_batch_create", "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
@@ -83,6 +83,8 @@ def load(path: str = LIB_PATH):
     lib.rteom_step.argtypes = [c.c_void_p, c.c_double, c.c_int32, _ip]
     lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_spectral.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
+    lib.rteom_checkpoint.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.POINTER(c.c_size_t)]
+    lib.rteom_restore.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t]
     lib.rteom_dims.argtypes = [c.c_void_p, _ip, _ip, _ip, _ip]
     lib.rteom_set_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
     lib.rteom_get_amplitudes.argtypes = [c.c_void_p, _dp, _dp]
@@ -190,6 +192,22 @@ class Propagator:
         st = self.lib.rteom_cumulant(self.h, total, _ptr(t), _ptr(c), ctypes.byref(n))
         self._check(st, self.h)
         return t[: n.value], c[: n.value, 0] + 1j * c[: n.value, 1]
+
+    def checkpoint(self):
+        """Image of the propagation state (amplitudes, C/E histories, times) as bytes."""
+        n = ctypes.c_size_t()
+        st = self.lib.rteom_checkpoint(self.h, None, 0, ctypes.byref(n))
+        self._check(st, self.h)
+        buf = ctypes.create_string_buffer(n.value)
+        st = self.lib.rteom_checkpoint(self.h, buf, n.value, ctypes.byref(n))
+        self._check(st, self.h)
+        return buf.raw
+
+    def restore(self, image):
+        """Continue from an image written by checkpoint() (same system)."""
+        data = bytes(image)
+        st = self.lib.rteom_restore(self.h, data, len(data))
+        self._check(st, self.h)
 
     def spectral(self, omegas, eta, e_corr=0.0):
         """(A(omega), qp position, A at the grid maximum) from the device C(t) (rteom_spectral)."""

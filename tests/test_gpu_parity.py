@@ -203,6 +203,23 @@ def test_tile_shape_choice_is_bit_identical(prec):
     assert np.array_equal(r[1], r[3])
 
 
+def test_checkpoint_restart_with_graph_replay():
+    """Checkpoint after 10 graph-replayed steps of the tiny workload, restore into a fresh
+    graph-mode context (whose captured step reads the step counter from the device) and
+    continue: C(t) and the amplitudes equal the uninterrupted run bit for bit."""
+    eps, chol = draw_system(TINY, cfg=0)
+    a = _prop(eps, chol, 4, 4, 0, 1, fixed_iters=3, graph=True, max_steps=64)
+    a.step(0.025, 10)
+    img = a.checkpoint()
+    a.step(0.025, 10)
+    b = _prop(eps, chol, 4, 4, 0, 1, fixed_iters=3, graph=True, max_steps=64)
+    b.step(0.025, 3)           # some other history first: the restore replaces it
+    b.restore(img)
+    b.step(0.025, 10)
+    assert np.array_equal(a.cumulant()[1], b.cumulant()[1])
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
+
+
 def test_batch_of_uneven_systems_matches_sequential():
     """Three uneven core-hole systems in one graph launch per step equal their separate runs."""
     shapes = [Shape(3, 9, 20), Shape(4, 14, 40), Shape(5, 11, 30)]

@@ -118,3 +118,37 @@ def test_spectral_function_vs_oracle():
     assert amax == a.max()
     with pytest.raises(rteom.RteomError):
         P.spectral(w, -1.0)
+
+
+def test_checkpoint_restart_continues_bitwise():
+    """A propagation checkpointed after 6 steps and restored into a fresh context continues
+    exactly as the uninterrupted one; foreign or truncated images are rejected, and a
+    restore clears the failed state left by a non-converged step."""
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=6, chol_scale=2.0)
+    a = rteom.Propagator(eps, chol, 3, 3, 0, 1, fixed_iters=3, lib_path=LIB)
+    a.step(0.05, 6)
+    img = a.checkpoint()
+    a.step(0.05, 4)
+    b = rteom.Propagator(eps, chol, 3, 3, 0, 1, fixed_iters=3, lib_path=LIB)
+    b.restore(img)
+    tb, cb = b.cumulant()
+    assert len(tb) == 7 and tb[-1] == a.cumulant()[0][6]
+    b.step(0.05, 4)
+    assert np.array_equal(a.cumulant()[1], b.cumulant()[1])
+    assert np.array_equal(a.cumulant()[0], b.cumulant()[0])
+    assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
+    other = rteom.Propagator(*draw_system(Shape(3, 6, 12), cfg=6), 3, 3, 0, 1, lib_path=LIB)
+    for bad in (img[:40], img[:-8], b"x" * len(img)):
+        with pytest.raises(rteom.RteomError) as ex:
+            b.restore(bad)
+        assert ex.value.status == 1
+    with pytest.raises(rteom.RteomError):
+        other.restore(img)
+    c = rteom.Propagator(eps, chol, 3, 3, 0, 1, tol=1e-14, max_iter=2, lib_path=LIB)
+    with pytest.raises(rteom.RteomError):
+        c.step(0.05, 1)
+    with pytest.raises(rteom.RteomError) as ex:
+        c.checkpoint()
+    assert ex.value.status == 6          # failed state
+    c.restore(img)
+    assert c.checkpoint() == img         # usable again, same state bit for bit

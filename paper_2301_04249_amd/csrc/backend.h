@@ -131,7 +131,8 @@ class Backend {
   // (outside capture) and keep the fastest, 0 = work-per-byte rule.
   virtual void set_tuning(int on) { (void)on; }
   // Test hook: force one tile shape (0: 64x64, 1: 64x128, 2: 128x64,
-  // 3: 128x128) where the operand types allow it; -1 = automatic.
+  // 3: 128x128, 4: 64x128 and 5: 128x64 with eight waves) where the operand
+  // types and precision allow it (else 64x64); -1 = automatic.
   virtual void force_tile(int v) { (void)v; }
   // total milliseconds and operation count of the profiled phase since the last call
   virtual double phase_ms(int ph, int64_t* ops) { (void)ph; if (ops) *ops = 0; return 0.0; }

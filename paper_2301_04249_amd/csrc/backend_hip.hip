@@ -99,18 +99,23 @@ template <> struct Mfma<float> {
   static __device__ inline int row(int lane, int r) { return 4 * (lane >> 4) + r; }
 };
 
-// Work-group tile (32*WM) x (32*WN): four waves in a 2 x 2 arrangement, each
-// holding WM x WN accumulator blocks of 16 x 16.  Wider tiles stage fewer
+// Work-group tile (16*WM*GM) x (16*WN*GN): GM x GN waves, each holding WM x WN
+// accumulator blocks of 16 x 16.  Wider tiles stage fewer
 // operand bytes per MFMA; the complex x complex product already has four MFMAs
 // per staged fragment pair and keeps 64 x 64.
 // S is the operand storage type: double, or float for operands converted to
 // float planes before the product (their pointers travel in the double fields of
 // GemmArgs and their strides count floats).
-template <typename T, typename S, bool AC, bool BC, bool AKC, bool BKC, int WM, int WN>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_mfma(GemmArgs g) {
+// GM x GN waves (4 or 8) per work-group; with 8 waves each holds 2 x 2 blocks and
+// uses at most 128 registers, so four waves share a SIMD and hide each other's
+// LDS and barrier waits.
+template <typename T, typename S, bool AC, bool BC, bool AKC, bool BKC, int WM, int WN, int GM = 2, int GN = 2>
+__global__ __launch_bounds__(64 * GM * GN)
+    __attribute__((amdgpu_waves_per_eu(GM * GN == 8 ? 4 : 2, 8))) void gemm_mfma(GemmArgs g) {
   typedef typename Mfma<T>::acc_t acc_t;
-  constexpr int TM = 32 * WM, TN = 32 * WN;
-  constexpr int NA = TM * BK / kThreads, NB = TN * BK / kThreads;   // staged elements per thread and plane
+  constexpr int NT = 64 * GM * GN;
+  constexpr int TM = 16 * WM * GM, TN = 16 * WN * GN;
+  constexpr int NA = TM * BK / NT, NB = TN * BK / NT;   // staged elements per thread and plane
   // LDS tiles: a k-contiguous operand is kept [row][BK + 1] (odd stride: the
   // coalesced writes and the fragment reads are both free of bank conflicts),
   // otherwise [k][row + 16] (the two 16-lane halves of a read hit disjoint banks).
@@ -125,15 +130,15 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave / GN, wn = wave % GN;
   int64_t tm, tn;
   tile_coords(g, blockIdx.x, tm, tn);
   const int64_t m0 = tm * TM, n0 = tn * TN;
   // Staging: element r of this thread sits at (row, k) = (am0 + r * AMS, ak0 + r * AKS)
   // of the A tile (likewise for B), so one base offset per operand and strides
   // that are the same for every thread address all of them.
-  constexpr int AMS = AKC ? 16 : 0, AKS = AKC ? 0 : kThreads / TM;
-  constexpr int BNS = BKC ? 16 : 0, BKS = BKC ? 0 : kThreads / TN;
+  constexpr int AMS = AKC ? NT / 16 : 0, AKS = AKC ? 0 : NT / TM;
+  constexpr int BNS = BKC ? NT / 16 : 0, BKS = BKC ? 0 : NT / TN;
   const int am0 = AKC ? (tid >> 4) : (tid % TM), ak0 = AKC ? (tid & 15) : (tid / TM);
   const int bn0 = BKC ? (tid >> 4) : (tid % TN), bk0 = BKC ? (tid & 15) : (tid / TN);
   const int lda0 = A_at(ak0, am0), ldb0 = B_at(bk0, bn0);
@@ -210,9 +215,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
       // float64: the wave multiplying runs at raised priority, so that its MFMA
       // chain is not held up by the other wave on the SIMD staging its next tile
       if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
-      // Wide tiles keep fragments of one (float64) or two (float32) k-steps in
-      // flight instead of four: the accumulators fill most of the register file.
-#pragma unroll (WM * WN <= 4 ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
+      // Wide per-wave tiles and 8-wave work-groups keep fragments of one (float64)
+      // or two (float32) k-steps in flight instead of four (register budget).
+#pragma unroll ((WM * WN <= 4 && GM * GN == 4) ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         T a_r[WM], a_i[WM], b_r[WN], b_i[WN];
@@ -1064,9 +1069,10 @@ __global__ __launch_bounds__(kPeakThreads) void qp_kernel(const double* a, const
   }
 }
 
-// Tile shapes of gemm_mfma: 0 = 64x64, 1 = 64x128, 2 = 128x64, 3 = 128x128.
-constexpr int kTiles = 4;
-constexpr int kTileM[kTiles] = {64, 64, 128, 128}, kTileN[kTiles] = {64, 128, 64, 128};
+// Tile shapes of gemm_mfma: 0 = 64x64, 1 = 64x128, 2 = 128x64, 3 = 128x128 (four
+// waves), 4 = 64x128 and 5 = 128x64 with eight waves of 2 x 2 blocks.
+constexpr int kTiles = 6;
+constexpr int kTileM[kTiles] = {64, 64, 128, 128, 64, 128}, kTileN[kTiles] = {64, 128, 64, 128, 128, 64};
 
 // Complex x complex keeps 64x64 (four MFMAs per staged fragment pair already).
 // A complex x real product widens only the real operand's side: widening the
@@ -1074,63 +1080,80 @@ constexpr int kTileM[kTiles] = {64, 64, 128, 128}, kTileN[kTiles] = {64, 128, 64
 // 128x128 holds 16 accumulator blocks: real x real in float32 only (in float64
 // they exceed the registers of two waves per SIMD).  The bf16x3 kernel has one
 // tile shape.
+// The eight-wave shapes are built for float64 (the float32 path already keeps
+// three or four waves per SIMD).
 inline bool tile_allowed(int v, int prec, bool ac, bool bc) {
   if (v < 0 || v >= kTiles) return false;
+  if (v >= 4 && prec != 0) return false;
   if (prec == 2 || (ac && bc)) return v == 0;
-  if (ac) return v == 0 || v == 1;
-  if (bc) return v == 0 || v == 2;
-  return v < 3 || prec == 1;
+  if (ac) return v == 0 || v == 1 || v == 4;
+  if (bc) return v == 0 || v == 2 || v == 5;
+  return v != 3 || prec == 1;
 }
 
-template <typename T, bool AC, bool BC, int WM, int WN>
-void launch_mfma_tile(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if (akc && bkc) gemm_mfma<T, double, AC, BC, true, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else if (akc) gemm_mfma<T, double, AC, BC, true, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else if (bkc) gemm_mfma<T, double, AC, BC, false, true, WM, WN><<<grid, kThreads, 0, st>>>(g);
-  else gemm_mfma<T, double, AC, BC, false, false, WM, WN><<<grid, kThreads, 0, st>>>(g);
+// Launchers return false when no kernel is built for the requested tile shape and
+// operand mix; the caller turns that into an error (never a silent fallback: the
+// grid was sized for the requested shape).
+template <typename T, bool AC, bool BC, int WM, int WN, int GM = 2, int GN = 2>
+bool launch_mfma_tile(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  constexpr int nt = 64 * GM * GN;
+  if (akc && bkc) gemm_mfma<T, double, AC, BC, true, true, WM, WN, GM, GN><<<grid, nt, 0, st>>>(g);
+  else if (akc) gemm_mfma<T, double, AC, BC, true, false, WM, WN, GM, GN><<<grid, nt, 0, st>>>(g);
+  else if (bkc) gemm_mfma<T, double, AC, BC, false, true, WM, WN, GM, GN><<<grid, nt, 0, st>>>(g);
+  else gemm_mfma<T, double, AC, BC, false, false, WM, WN, GM, GN><<<grid, nt, 0, st>>>(g);
+  return true;
+}
+
+template <typename T, bool AC, bool BC>
+bool launch_mfma(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (v == 0) return launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+  if constexpr (!BC) {   // the real B side widens
+    if (v == 1) return launch_mfma_tile<T, AC, BC, 2, 4>(grid, st, g, akc, bkc);
+    if constexpr (sizeof(T) == 8) {
+      if (v == 4) return launch_mfma_tile<T, AC, BC, 2, 2, 2, 4>(grid, st, g, akc, bkc);
+    }
+  }
+  if constexpr (!AC) {   // the real A side widens
+    if (v == 2) return launch_mfma_tile<T, AC, BC, 4, 2>(grid, st, g, akc, bkc);
+    if constexpr (sizeof(T) == 8) {
+      if (v == 5) return launch_mfma_tile<T, AC, BC, 2, 2, 4, 2>(grid, st, g, akc, bkc);
+    }
+  }
+  if constexpr (sizeof(T) == 4 && !AC && !BC) {
+    if (v == 3) return launch_mfma_tile<T, AC, BC, 4, 4>(grid, st, g, akc, bkc);
+  }
+  return false;
 }
 
 // float operands converted before the product: both k-contiguous
 template <bool AC, bool BC>
-void launch_f32_converted(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if constexpr (AC && BC) {
+bool launch_f32_converted(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if (v == 0) {
     gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
-  } else if constexpr (AC) {
-    if (v == 1) gemm_mfma<float, float, AC, BC, true, true, 2, 4><<<grid, kThreads, 0, st>>>(g);
-    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
-  } else if constexpr (BC) {
-    if (v == 2) gemm_mfma<float, float, AC, BC, true, true, 4, 2><<<grid, kThreads, 0, st>>>(g);
-    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
-  } else {
-    if (v == 1) gemm_mfma<float, float, AC, BC, true, true, 2, 4><<<grid, kThreads, 0, st>>>(g);
-    else if (v == 2) gemm_mfma<float, float, AC, BC, true, true, 4, 2><<<grid, kThreads, 0, st>>>(g);
-    else if (v == 3) gemm_mfma<float, float, AC, BC, true, true, 4, 4><<<grid, kThreads, 0, st>>>(g);
-    else gemm_mfma<float, float, AC, BC, true, true, 2, 2><<<grid, kThreads, 0, st>>>(g);
+    return true;
   }
-}
-
-void launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc);
-
-template <typename T, bool AC, bool BC>
-void launch_mfma(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if constexpr (AC && BC) {
-    launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
-  } else if constexpr (AC) {
-    if (v == 1) launch_mfma_tile<T, AC, BC, 2, 4>(grid, st, g, akc, bkc);
-    else launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
-  } else if constexpr (BC) {
-    if (v == 2) launch_mfma_tile<T, AC, BC, 4, 2>(grid, st, g, akc, bkc);
-    else launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
-  } else {
-    if (v == 1) launch_mfma_tile<T, AC, BC, 2, 4>(grid, st, g, akc, bkc);
-    else if (v == 2) launch_mfma_tile<T, AC, BC, 4, 2>(grid, st, g, akc, bkc);
-    else if (v == 3 && sizeof(T) == 4) {
-      if constexpr (sizeof(T) == 4) launch_mfma_tile<T, AC, BC, 4, 4>(grid, st, g, akc, bkc);
-    } else {
-      launch_mfma_tile<T, AC, BC, 2, 2>(grid, st, g, akc, bkc);
+  if constexpr (!BC) {
+    if (v == 1) {
+      gemm_mfma<float, float, AC, BC, true, true, 2, 4><<<grid, kThreads, 0, st>>>(g);
+      return true;
     }
   }
+  if constexpr (!AC) {
+    if (v == 2) {
+      gemm_mfma<float, float, AC, BC, true, true, 4, 2><<<grid, kThreads, 0, st>>>(g);
+      return true;
+    }
+  }
+  if constexpr (!AC && !BC) {
+    if (v == 3) {
+      gemm_mfma<float, float, AC, BC, true, true, 4, 4><<<grid, kThreads, 0, st>>>(g);
+      return true;
+    }
+  }
+  return false;
 }
+
+bool launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc);
 
 template <bool AC, bool BC>
 void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
@@ -1146,56 +1169,57 @@ constexpr int split_lds_bytes(bool ac, bool bc, int v) {
   return 2 * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
 }
 inline bool split_tile_allowed(int v, bool ac, bool bc) {
-  return v >= 0 && v < kTiles && split_lds_bytes(ac, bc, v) <= 80 * 1024;
+  return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v) <= 80 * 1024;
 }
 
 template <bool AC, bool BC, int WM, int WN, int V>
-void launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if constexpr (split_lds_bytes(AC, BC, V) <= 80 * 1024) gemm_bf16x3_split<AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
-}
-
-template <bool AC, bool BC>
-void launch_split(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if (v == 1) launch_split_tile<AC, BC, 2, 4, 1>(grid, st, g);
-  else if (v == 2) launch_split_tile<AC, BC, 4, 2, 2>(grid, st, g);
-  else if (v == 3) launch_split_tile<AC, BC, 4, 4, 3>(grid, st, g);
-  else launch_split_tile<AC, BC, 2, 2, 0>(grid, st, g);
-}
-
-void launch_split_gemm(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
-  if (ac && bc) launch_split<true, true>(v, grid, st, g);
-  else if (ac) launch_split<true, false>(v, grid, st, g);
-  else if (bc) launch_split<false, true>(v, grid, st, g);
-  else launch_split<false, false>(v, grid, st, g);
-}
-
-void launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
-  if (prec == 2) {
-    launch_split_gemm(v, grid, st, g, ac, bc);
-  } else if (ac && bc) {
-    launch_f32_converted<true, true>(v, grid, st, g);
-  } else if (ac) {
-    launch_f32_converted<true, false>(v, grid, st, g);
-  } else if (bc) {
-    launch_f32_converted<false, true>(v, grid, st, g);
-  } else {
-    launch_f32_converted<false, false>(v, grid, st, g);
+bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if constexpr (split_lds_bytes(AC, BC, V) <= 80 * 1024) {
+    gemm_bf16x3_split<AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
+    return true;
   }
+  return false;
 }
 
 template <bool AC, bool BC>
-void launch_prec(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
-  if (prec == 0) launch_mfma<double, AC, BC>(v, grid, st, g, akc, bkc);
-  else if (prec == 1) launch_mfma<float, AC, BC>(v, grid, st, g, akc, bkc);
-  else launch_bf16x3<AC, BC>(grid, st, g, akc, bkc);
+bool launch_split(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
+  if (v == 0) return launch_split_tile<AC, BC, 2, 2, 0>(grid, st, g);
+  if (v == 1) return launch_split_tile<AC, BC, 2, 4, 1>(grid, st, g);
+  if (v == 2) return launch_split_tile<AC, BC, 4, 2, 2>(grid, st, g);
+  if (v == 3) return launch_split_tile<AC, BC, 4, 4, 3>(grid, st, g);
+  return false;
 }
 
-void launch_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc, bool akc,
+bool launch_split_gemm(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
+  if (ac && bc) return launch_split<true, true>(v, grid, st, g);
+  if (ac) return launch_split<true, false>(v, grid, st, g);
+  if (bc) return launch_split<false, true>(v, grid, st, g);
+  return launch_split<false, false>(v, grid, st, g);
+}
+
+bool launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
+  if (prec == 2) return launch_split_gemm(v, grid, st, g, ac, bc);
+  if (ac && bc) return launch_f32_converted<true, true>(v, grid, st, g);
+  if (ac) return launch_f32_converted<true, false>(v, grid, st, g);
+  if (bc) return launch_f32_converted<false, true>(v, grid, st, g);
+  return launch_f32_converted<false, false>(v, grid, st, g);
+}
+
+template <bool AC, bool BC>
+bool launch_prec(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool bkc) {
+  if (prec == 0) return launch_mfma<double, AC, BC>(v, grid, st, g, akc, bkc);
+  if (prec == 1) return launch_mfma<float, AC, BC>(v, grid, st, g, akc, bkc);
+  if (v != 0) return false;
+  launch_bf16x3<AC, BC>(grid, st, g, akc, bkc);
+  return true;
+}
+
+bool launch_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc, bool akc,
                  bool bkc) {
-  if (ac && bc) launch_prec<true, true>(prec, v, grid, st, g, akc, bkc);
-  else if (ac) launch_prec<true, false>(prec, v, grid, st, g, akc, bkc);
-  else if (bc) launch_prec<false, true>(prec, v, grid, st, g, akc, bkc);
-  else launch_prec<false, false>(prec, v, grid, st, g, akc, bkc);
+  if (ac && bc) return launch_prec<true, true>(prec, v, grid, st, g, akc, bkc);
+  if (ac) return launch_prec<true, false>(prec, v, grid, st, g, akc, bkc);
+  if (bc) return launch_prec<false, true>(prec, v, grid, st, g, akc, bkc);
+  return launch_prec<false, false>(prec, v, grid, st, g, akc, bkc);
 }
 
 int grid_for(int64_t n, int per_block = 256) {
@@ -1334,8 +1358,13 @@ class HipBackend : public Backend {
     if (v < 0) { end(); return; }
     dim3 grid;
     if (!shape_grid(g, v, op.batch, &grid)) { end(); return; }
-    if (presplit) launch_converted_gemm(op.prec, v, grid, stream_, g, ac, bc);
-    else launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
+    const bool ok = presplit ? launch_converted_gemm(op.prec, v, grid, stream_, g, ac, bc)
+                             : launch_gemm(op.prec, v, grid, stream_, g, ac, bc, akc, bkc);
+    if (!ok) {
+      set_err("gemm: no kernel for tile shape " + std::to_string(v) + " with these operands");
+      end();
+      return;
+    }
     launched("gemm");
     if (g.splitk > 1) {
       splitk_reduce<<<grid_for(op.M * op.N), 256, 0, stream_>>>(g, cplx ? 1 : 0);
@@ -1464,8 +1493,12 @@ class HipBackend : public Backend {
         dim3 grid;
         if (!shape_grid(gt, cand[i], op.batch, &grid)) return -1;
         record(hipEventRecord(tune_a_, stream_), "hipEventRecord");
-        if (presplit) launch_converted_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc);
-        else launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
+        const bool ok = presplit ? launch_converted_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc)
+                                 : launch_gemm(op.prec, cand[i], grid, stream_, gt, ac, bc, akc, bkc);
+        if (!ok) {
+          set_err("gemm: no kernel for tile shape " + std::to_string(cand[i]) + " with these operands");
+          return -1;
+        }
         launched("gemm (tuning)");
         record(hipEventRecord(tune_b_, stream_), "hipEventRecord");
         record(hipEventSynchronize(tune_b_), "hipEventSynchronize");

@@ -24,13 +24,17 @@ import numpy as np  # noqa: E402
 from synthetic import ESCA_PAPER, FORMALDEHYDE, TINY, batched_shapes, draw_system  # noqa: E402
 
 # Ladder kernel per precision (the contraction's MFMA instruction family)
-KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float>", "bf16x3": "gemm_bf16x3"}
+KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands converted to float planes)",
+               "bf16x3": "gemm_bf16x3_split (operands split into bf16 hi/lo planes)"}
 
 # HBM bytes per ladder launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # scaled by the same counters read on a plain device copy of known size; the
 # summaries (with the commands) are under profiles/.  Only workloads whose
 # ladder kernel has been counted since its last change are listed.
-TRAFFIC = {}
+TRAFFIC = {
+    # profiles/gemm_mfma_ladder_esca_fp64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch
+    ("esca", "fp64"): 5.021e12,
+}
 
 DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",
          "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}

@@ -3,6 +3,8 @@
 librteom.so            the product: C ABI + engine + gfx950 HIP kernels.
 librteom_hostcheck.so  test build of the same engine over host loops (tests/_hostcheck/),
                        used only by CPU tests of the host logic; never loaded by the package.
+kernel_probe           test program (tests/kernel_probe/) that checks the GEMM and permute
+                       kernels of librteom.so against host loops; run by a GPU test.
 
 Run ``python -m paper_2301_04249_amd.build`` (or ``__graft_entry__.build()``).
 """
@@ -60,9 +62,19 @@ def build_hostcheck():
     return out
 
 
+def build_probe():
+    d = os.path.join(ROOT, "tests", "kernel_probe")
+    out = os.path.join(d, "kernel_probe")
+    _run([HIPCC, "-O2", "-std=c++17", os.path.join(d, "kernel_probe.cpp"), f"-L{HERE}", "-l:librteom.so",
+          "-Wl,-rpath,$ORIGIN/../../paper_2301_04249_amd", "-o", out + ".tmp"])
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def main():
     build_product()
     build_hostcheck()
+    build_probe()
 
 
 if __name__ == "__main__":

@@ -122,6 +122,20 @@ def n_minus_one_reference(eps, chol, n_occ_a: int, n_occ_b: int, core_orb: int,
                              fock=fock, g=g)
 
 
+def closed_shell_reference(eps, chol, n_occ_a: int, n_occ_b: int, lean: bool = False) -> SpinOrbitalSystem:
+    """The N-electron determinant itself (no ionisation), whose ground-state correlation
+    energy E_N^corr enters G(tau) (Sec. 2.2).  The orbital energies are its Fock diagonal:
+    f_pq = eps_p delta_pq.  ``core`` is -1."""
+    eps = np.asarray(eps, dtype=np.float64)
+    chol = np.asarray(chol, dtype=np.float64)
+    n = eps.shape[0]
+    occ = np.array([p for p in range(n_occ_a)] + [p + n for p in range(n_occ_b)], dtype=np.int64)
+    vir = np.array(sorted(set(range(2 * n)) - set(occ.tolist())), dtype=np.int64)
+    g = None if lean else antisymmetrized_spin_orbital(coulomb_from_cholesky(chol))
+    return SpinOrbitalSystem(n=n, eps=eps, chol=chol, occ=occ, vir=vir, core=-1,
+                             fock=np.diag(np.concatenate([eps, eps])), g=g)
+
+
 def one_body_core(sys: SpinOrbitalSystem) -> np.ndarray:
     """h_pq implied by the Fock matrix of Phi: h = f - sum_{k in occ(Phi)} <pk||qk>."""
     return sys.fock - np.einsum("pkqk->pq", sys.g[:, sys.occ][:, :, :, sys.occ])

@@ -361,3 +361,34 @@ def test_size_extensivity_of_residual_and_energy():
     assert np.abs(r1[~covered1]).max() < 1e-13
     assert np.abs(r2[~covered2]).max() < 1e-13
     assert abs(ccsd.energy(big, t1, t2) - e_sum) < 1e-12
+
+
+def test_ground_state_ccsd_exact_for_two_electrons():
+    """Ground-state CCSD (E_N^corr for G(tau)) is full CI for two electrons: the correlation
+    energy equals the lowest eigenvalue of H in the two-electron sector minus <Phi|H|Phi>."""
+    from oracle import groundstate
+    eps, chol = draw_system(Shape(1, 5, 14), cfg=77, chol_scale=2.0)
+    sysm = reference.closed_shell_reference(eps, chol, 1, 1)
+    e_cc, t1, t2, it = groundstate.solve(sysm, tol=1e-13, max_iter=500)
+    sector = fockspace.Sector(sysm.nso, 2)
+    H = fockspace.hamiltonian(sysm, sector)
+    ref = sector.index[fockspace.reference_det(sysm)]
+    e_fci = np.linalg.eigvalsh(H)[0] - H[ref, ref]
+    assert abs(e_cc.imag) < 1e-14
+    assert e_fci < -1e-3                         # a correlated case
+    assert abs(e_cc.real - e_fci) < 1e-10 * abs(e_fci)
+    assert np.abs(t1.imag).max() == 0 and np.abs(t2.imag).max() == 0
+
+
+def test_ground_state_ccsd_weak_coupling_is_mp2():
+    """As the integrals are scaled down by lam, E_CCSD / E_MP2 - 1 = O(lam^2) (MP3 and
+    higher orders): the deviation drops ~4x per halving of lam."""
+    from oracle import groundstate
+    devs = []
+    for lam in (0.2, 0.1, 0.05):
+        eps, chol = draw_system(Shape(3, 5, 12), cfg=78, chol_scale=lam)
+        sysm = reference.closed_shell_reference(eps, chol, 3, 3)
+        e_cc = groundstate.solve(sysm, tol=1e-15, max_iter=500)[0].real
+        devs.append(abs(e_cc / groundstate.mp2_energy(sysm) - 1.0))
+    assert devs[0] / devs[1] > 3.0 and devs[1] / devs[2] > 3.0
+    assert devs[2] < 1e-3

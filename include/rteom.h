@@ -102,8 +102,10 @@ rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ
    fock_diag: host [n_orb], the N-electron orbital energies eps_p (Fock diagonal).
    chol:      host [n_chol][n_orb][n_orb], Cholesky vectors L^Q_pq, symmetric in (p,q).
    core_orb/core_spin: the ionised spin-orbital c (spatial index occupied in that spin,
-   0 = alpha, 1 = beta).  Builds the (N-1) Fock matrix and the integral blocks on the
-   device; T(0) = 0 and C(0) = 0.  The caller may free the host arrays afterwards.
+   0 = alpha, 1 = beta); core_orb = -1 makes the N-electron determinant itself the
+   reference (no ionisation, core_spin ignored: for rteom_ground_state).  Builds the
+   Fock matrix of the reference and the integral blocks on the device; T(0) = 0 and
+   C(0) = 0.  The caller may free the host arrays afterwards.
    Errors: ARG (sizes, indices, non-symmetric L), NONFINITE, OOM, HIP. */
 rteom_status rteom_init(rteom_ctx** ctx, int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
                         const double* fock_diag, int32_t n_chol, const double* chol,
@@ -121,6 +123,17 @@ rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* mic
    cap = 0 is a length query: nothing is written and *n_out = steps taken + 1. */
 rteom_status rteom_cumulant(const rteom_ctx* ctx, int64_t cap, double* t_out, double* c_out,
                             int64_t* n_out);
+
+/* Ground-state CCSD of the reference (Sec. 2.2: the correlation energy E_N^corr of the
+   N-electron ground state enters the phase of G(t), see rteom_spectral): solves
+   R(T) = 0 (Eqs. dt1eom, dt2eom with the left side zero) by Jacobi iteration
+   T <- T + R(T) / D (D the orbital-energy denominators), from T = 0, until the largest
+   change of an amplitude is below tol, and writes E^corr = <Phi|(H_N e^T)_C|Phi>
+   (Eq. cum_gf3's integrand) to host e_corr [2] = (re, im).  Meant for a context created
+   with core_orb = -1; the converged amplitudes replace the context's (the C(t) history
+   is untouched).  iters (nullable): Jacobi iterations used.  ARG for tol <= 0 or
+   max_iter < 1; NOCONV / NONFINITE leave the context in a failed state. */
+rteom_status rteom_ground_state(rteom_ctx* ctx, double tol, int32_t max_iter, double* e_corr, int32_t* iters);
 
 /* Checkpoint and restart of a propagation (Sec. 3: runs of hundreds of atomic time units
    need restarts).  The image holds the amplitudes T(t_n), the C(t) and E(t) histories and
@@ -151,7 +164,8 @@ rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len);
    grid maximum and its two neighbours; A at the grid maximum).  Computed on the
    device (temporary device memory of (3 n + 2 n_w + 2) doubles, n = steps + 1);
    synchronises the stream.  ARG for NULL omega/a_out, n_w < 1, non-finite
-   input or eta < 0; OOM if the temporary cannot be allocated. */
+   input, eta < 0 or a context without a core hole; OOM if the temporary cannot be
+   allocated. */
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out);
 

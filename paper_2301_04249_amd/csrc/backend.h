@@ -84,6 +84,7 @@ struct SpinVectors {
 //   start: rhs = x + i h r; then for every amplitude
 //   plain:       x' = rhs + i h r
 //   denominator: x' = (rhs + i h (r + D x)) / (1 + i h D)
+//   Jacobi:      x' = x + r / D   (mode 2, ground state R(T) = 0; rhs unused)
 //   x' = 0 where the spin-orbital does not exist;  *delta = max |x' - x|.
 struct UpdateOp {
   AmpLayout lay;
@@ -91,7 +92,7 @@ struct UpdateOp {
   const double* r_re = nullptr; const double* r_im = nullptr;
   double* rhs_re = nullptr; double* rhs_im = nullptr;
   double h = 0.0;      // dt / 2
-  int mode = 0;        // 0 plain, 1 denominator
+  int mode = 0;        // 0 plain, 1 denominator, 2 Jacobi
   int start = 0;       // 1: write rhs from x and r first
   SpinVectors sv;
   double* delta = nullptr;  // device double, max-reduced (caller zeroes it)

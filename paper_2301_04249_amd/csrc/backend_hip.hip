@@ -862,26 +862,32 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs u) {
       dd = u.fo[s1][i] + u.fo[s2][j] - u.fv[s1][a] - u.fv[s2][b];
     }
     const double xr = u.xr[k], xi = u.xi[k], rr = u.rr[k], ri = u.ri[k];
-    double hr, hi;
-    if (u.start) {
-      hr = xr - u.h * ri;
-      hi = xi + u.h * rr;
-      u.hr_[k] = hr;
-      u.hi_[k] = hi;
-    } else {
-      hr = u.hr_[k];
-      hi = u.hi_[k];
-    }
     double nr, ni;
-    if (u.mode == 0) {
-      nr = hr - u.h * ri;
-      ni = hi + u.h * rr;
+    if (u.mode == 2) {
+      // Jacobi step towards R(T) = 0 (ground state): x + r / D
+      nr = dd != 0.0 ? xr + rr / dd : 0.0;
+      ni = dd != 0.0 ? xi + ri / dd : 0.0;
     } else {
-      const double pr = rr + dd * xr, pi = ri + dd * xi;
-      const double numr = hr - u.h * pi, numi = hi + u.h * pr;
-      const double di = u.h * dd, den = 1.0 + di * di;
-      nr = (numr + numi * di) / den;
-      ni = (numi - numr * di) / den;
+      double hr, hi;
+      if (u.start) {
+        hr = xr - u.h * ri;
+        hi = xi + u.h * rr;
+        u.hr_[k] = hr;
+        u.hi_[k] = hi;
+      } else {
+        hr = u.hr_[k];
+        hi = u.hi_[k];
+      }
+      if (u.mode == 0) {
+        nr = hr - u.h * ri;
+        ni = hi + u.h * rr;
+      } else {
+        const double pr = rr + dd * xr, pi = ri + dd * xi;
+        const double numr = hr - u.h * pi, numi = hi + u.h * pr;
+        const double di = u.h * dd, den = 1.0 + di * di;
+        nr = (numr + numi * di) / den;
+        ni = (numi - numr * di) / den;
+      }
     }
     if (mask == 0.0) { nr = 0.0; ni = 0.0; }
     const double dr = nr - xr, dq = ni - xi;

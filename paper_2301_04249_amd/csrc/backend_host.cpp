@@ -111,6 +111,16 @@ class HostBackend : public Backend {
         dd = u.sv.fo[s1][i] + u.sv.fo[s2][j] - u.sv.fv[s1][a] - u.sv.fv[s2][b];
       }
       const double xr = u.x_re[k], xi = u.x_im[k], rr = u.r_re[k], ri = u.r_im[k];
+      if (u.mode == 2) {   // Jacobi step towards R(T) = 0
+        double nr = dd != 0.0 ? xr + rr / dd : 0.0, ni = dd != 0.0 ? xi + ri / dd : 0.0;
+        if (mask == 0.0) nr = ni = 0.0;
+        const double dr = nr - xr, di = ni - xi;
+        dmax = std::max(dmax, std::sqrt(dr * dr + di * di));
+        if (std::isnan(nr) || std::isnan(ni)) dmax = NAN;
+        u.x_re[k] = nr;
+        u.x_im[k] = ni;
+        continue;
+      }
       double hr, hi;  // rhs
       if (u.start) {
         hr = xr - u.h * ri;

@@ -121,7 +121,7 @@ struct Context {
       int ns = s == 0 ? na : nb;
       for (int p = 0; p < ns; ++p) occ[s][p] = 1;
     }
-    occ[core_spin][core_orb] = 0;
+    if (core_orb >= 0) occ[core_spin][core_orb] = 0;   // core_orb < 0: the N-electron determinant
     for (int s = 0; s < 2; ++s) {
       vir[s].assign(n, 0);
       for (int p = 0; p < n; ++p) vir[s][p] = !occ[s][p];
@@ -147,7 +147,7 @@ struct Context {
 
   void init(const double* eps, const double* chol) {
     setup_spaces();
-    if (eps) eps_core = eps[core_orb];
+    if (eps && core_orb >= 0) eps_core = eps[core_orb];
     eng.be = be;
     eng.scratch = &arena;
     eng.prec = RTEOM_FP64;   // integral blocks and Fock matrices: float64, once
@@ -205,16 +205,19 @@ struct Context {
     // Fock of Phi per spin: f_pq = eps_p delta_pq - <pc||qc> (Sec. 2.1):
     // -(pq|cc) for both spins, +(pc|cq) for the spin of c.  The small vectors
     // L^Q_cc and L^Q_pc (p over the extended space) are gathered on the host.
+    // (Without a core hole, core_orb < 0, f is the N-electron Fock matrix diag(eps).)
     View Lfull[2][2] = {{Lv(Loo, no, no), Lv(Lov, no, nv)}, {Lv(Lvo, nv, no), Lv(Lvv, nv, nv)}};
+    const bool hole = core_orb >= 0;
     double* Lcc = take(Q);
     double* Lxc = take(Q * nx);
     double* dev_eps = take(nx);
     if (!dry) {
-      std::vector<double> lcc(Q), lxc((size_t)Q * nx), epsx(nx);
-      for (int64_t q = 0; q < Q; ++q) {
-        lcc[q] = chol[((size_t)q * n + core_orb) * n + core_orb];
-        for (int p = 0; p < nx; ++p) lxc[(size_t)q * nx + p] = chol[((size_t)q * n + ext[p]) * n + core_orb];
-      }
+      std::vector<double> lcc(Q, 0.0), lxc((size_t)Q * nx, 0.0), epsx(nx);
+      if (hole)
+        for (int64_t q = 0; q < Q; ++q) {
+          lcc[q] = chol[((size_t)q * n + core_orb) * n + core_orb];
+          for (int p = 0; p < nx; ++p) lxc[(size_t)q * nx + p] = chol[((size_t)q * n + ext[p]) * n + core_orb];
+        }
       for (int p = 0; p < nx; ++p) epsx[p] = eps[ext[p]];
       h2d(Lcc, lcc.data(), Q);
       h2d(Lxc, lxc.data(), Q * nx);
@@ -229,6 +232,7 @@ struct Context {
         for (int Y1 = 0; Y1 < 2; ++Y1) {
           const int64_t r0 = X1 ? no : 0, c0 = Y1 ? no : 0, nr = X1 ? nv : no, nc = Y1 ? nv : no;
           View blk = fview(f[s], r0, c0, nr, nc, false);
+          if (!hole) continue;
           eng.contract("Qpq,Q->pq", Lfull[X1][Y1], vec(Lcc, Q), blk, -1.0, 1);
           if (s == core_spin)
             eng.contract("Qp,Qq->pq", block(Lxc_v, {0, r0}, {Q, nr}), block(Lxc_v, {0, c0}, {Q, nc}), blk, 1.0, 1);
@@ -577,6 +581,29 @@ struct Context {
     return opt.fp_fixed_iters;
   }
 
+  // Ground-state CCSD (R(T) = 0) by Jacobi iteration from T = 0; e_out = E^corr.
+  int ground_state(double tol, int max_iter, double* e_out) {
+    be->fill(X, 2 * lay.size(), 0.0);
+    UpdateOp u = update_op(false);
+    u.mode = 2;
+    for (int it = 1; it <= max_iter; ++it) {
+      residual(X, R);
+      be->set_phase(kPhaseUpdate);
+      be->fill(delta, 1, 0.0);
+      be->update(u);
+      double d = 0.0;
+      be->d2h(&d, delta, sizeof(double));
+      if (!std::isfinite(d)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitudes in the ground-state iteration");
+      if (d < tol) {
+        be->set_phase(kPhaseEnergy);
+        energy(X, e_next);
+        be->d2h(e_out, e_next, 2 * sizeof(double));
+        return it;
+      }
+    }
+    throw Error(RTEOM_ERR_NOCONV, "ground-state CCSD not converged in " + std::to_string(max_iter) + " iterations");
+  }
+
   int enqueue_step(double dt) {
     UpdateOp u0 = update_op(true);
     u0.h = 0.5 * dt;
@@ -673,9 +700,11 @@ rteom_status check_sizes(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_
                          int32_t core_orb, int32_t core_spin, std::string* m) {
   if (n_orb < 2 || n_chol < 1) { *m = "n_orb >= 2 and n_chol >= 1 required"; return RTEOM_ERR_ARG; }
   if (n_occ_a < 0 || n_occ_b < 0 || n_occ_a > n_orb || n_occ_b > n_orb) { *m = "bad occupation numbers"; return RTEOM_ERR_ARG; }
-  if (core_spin != 0 && core_spin != 1) { *m = "core_spin must be 0 (alpha) or 1 (beta)"; return RTEOM_ERR_ARG; }
-  const int nocc = core_spin == 0 ? n_occ_a : n_occ_b;
-  if (core_orb < 0 || core_orb >= nocc) { *m = "core orbital is not occupied in that spin"; return RTEOM_ERR_ARG; }
+  if (core_orb != -1) {   // -1: the N-electron determinant itself (no core hole)
+    if (core_spin != 0 && core_spin != 1) { *m = "core_spin must be 0 (alpha) or 1 (beta)"; return RTEOM_ERR_ARG; }
+    const int nocc = core_spin == 0 ? n_occ_a : n_occ_b;
+    if (core_orb < 0 || core_orb >= nocc) { *m = "core orbital is not occupied in that spin"; return RTEOM_ERR_ARG; }
+  }
   if (n_occ_a + n_occ_b < 2) { *m = "need at least two electrons"; return RTEOM_ERR_ARG; }
   return RTEOM_OK;
 }
@@ -931,10 +960,23 @@ rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len) {
   });
 }
 
+rteom_status rteom_ground_state(rteom_ctx* ctx, double tol, int32_t max_iter, double* e_corr, int32_t* iters) {
+  if (!ctx || !e_corr) { g_last_error = "NULL argument"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  if (!(tol > 0.0) || !std::isfinite(tol) || max_iter < 1) { c.err = "tol must be positive, max_iter >= 1"; return RTEOM_ERR_ARG; }
+  int passes = 0;
+  rteom_status st = guarded(ctx, [&] { passes = c.ground_state(tol, max_iter, e_corr); });
+  if (iters) *iters = passes;
+  if (st == RTEOM_ERR_NOCONV || st == RTEOM_ERR_NONFINITE || st == RTEOM_ERR_HIP) c.failed = true;
+  else if (st == RTEOM_OK) c.failed = false;
+  return st;
+}
+
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out) {
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
   Context& c = ctx->c;
+  if (c.core_orb < 0) { c.err = "the context has no core hole"; return RTEOM_ERR_ARG; }
   if (!omega || !a_out || n_w < 1) { c.err = "omega and a_out are required, n_w >= 1"; return RTEOM_ERR_ARG; }
   if (!std::isfinite(e_corr) || !std::isfinite(eta) || eta < 0.0) {
     c.err = "e_corr must be finite and eta finite and >= 0";

@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # every exported symbol of include/rteom.h
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
-    "rteom_spectral", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_spectral", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
     "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_batch_create", "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
@@ -83,6 +83,7 @@ def load(path: str = LIB_PATH):
     lib.rteom_step.argtypes = [c.c_void_p, c.c_double, c.c_int32, _ip]
     lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_spectral.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
+    lib.rteom_ground_state.argtypes = [c.c_void_p, c.c_double, c.c_int32, _dp, _ip]
     lib.rteom_checkpoint.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.POINTER(c.c_size_t)]
     lib.rteom_restore.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t]
     lib.rteom_dims.argtypes = [c.c_void_p, _ip, _ip, _ip, _ip]
@@ -192,6 +193,15 @@ class Propagator:
         st = self.lib.rteom_cumulant(self.h, total, _ptr(t), _ptr(c), ctypes.byref(n))
         self._check(st, self.h)
         return t[: n.value], c[: n.value, 0] + 1j * c[: n.value, 1]
+
+    def ground_state(self, tol=1e-10, max_iter=200):
+        """(E^corr, iterations) of ground-state CCSD for this reference (rteom_ground_state);
+        create the propagator with core_orb=-1 for the N-electron determinant."""
+        e = np.zeros(2)
+        it = ctypes.c_int32()
+        st = self.lib.rteom_ground_state(self.h, float(tol), int(max_iter), _ptr(e), ctypes.byref(it))
+        self._check(st, self.h)
+        return complex(e[0], e[1]), it.value
 
     def checkpoint(self):
         """Image of the propagation state (amplitudes, C/E histories, times) as bytes."""

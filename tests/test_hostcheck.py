@@ -152,3 +152,27 @@ def test_checkpoint_restart_continues_bitwise():
     assert ex.value.status == 6          # failed state
     c.restore(img)
     assert c.checkpoint() == img         # usable again, same state bit for bit
+
+
+def test_ground_state_and_no_hole_reference_vs_oracle():
+    """core_orb = -1: the N-electron determinant as reference.  Residual at random amplitudes
+    and the ground-state CCSD correlation energy (rteom_ground_state) against the oracle."""
+    from oracle import groundstate
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=79, chol_scale=1.0)
+    sysm = reference.closed_shell_reference(eps, chol, 3, 3)
+    P = rteom.Propagator(eps, chol, 3, 3, -1, 0, lib_path=LIB)
+    t1, t2 = blocks.random_spin_orbital_amplitudes(sysm, 9)
+    b1, b2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, t1, t2)
+    P.set_amplitudes(b1, b2)
+    r1, r2 = P.residual()
+    e1, e2 = blocks.to_blocks(sysm, P.occ_list, P.vir_list, *ccsd.residual(sysm, t1, t2))
+    assert np.abs(r1 - e1).max() < 1e-12 * max(1.0, np.abs(e2).max())
+    assert np.abs(r2 - e2).max() < 1e-12 * max(1.0, np.abs(e2).max())
+    e_ref, _, g2, it_ref = groundstate.solve(sysm, tol=1e-12)
+    e, it = P.ground_state(tol=1e-12)
+    assert it == it_ref
+    assert abs(e - e_ref) < 1e-12 * abs(e_ref)
+    _, gt2 = P.get_amplitudes()
+    assert np.abs(gt2 - blocks.to_blocks(sysm, P.occ_list, P.vir_list, np.zeros((sysm.no, sysm.nv)), g2)[1]).max() < 1e-12
+    with pytest.raises(rteom.RteomError):
+        P.spectral(np.linspace(-1, 1, 5), 0.1)      # no core hole

@@ -220,8 +220,8 @@ def test_checkpoint_restart_with_graph_replay():
     assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6), ("bf16x3", 1e-4)])
-def test_ground_state_ccsd(prec, tol):
+@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-6, 1e-8), ("bf16x3", 1e-4, 1e-6)])
+def test_ground_state_ccsd(prec, tol, solve_tol):
     """E_N^corr of the tiny workload's N-electron determinant (core_orb = -1) by
     rteom_ground_state against the oracle's Jacobi solution (relative error bound per
     precision; float64 also takes the same number of iterations)."""
@@ -230,7 +230,7 @@ def test_ground_state_ccsd(prec, tol):
     sysm = reference.closed_shell_reference(eps, chol, 4, 4)
     e_ref, _, _, it_ref = groundstate.solve(sysm, tol=1e-11)
     P = _prop(eps, chol, 4, 4, -1, 0, prec=prec)
-    e, it = P.ground_state(tol=1e-11)
+    e, it = P.ground_state(tol=solve_tol, max_iter=400)
     err = abs(e - e_ref) / abs(e_ref)
     print(f"{prec}: E_corr {e.real:.12f} vs oracle {e_ref.real:.12f} (rel err {err:.2e}), {it} iterations")
     assert err < tol

@@ -176,3 +176,19 @@ def test_ground_state_and_no_hole_reference_vs_oracle():
     assert np.abs(gt2 - blocks.to_blocks(sysm, P.occ_list, P.vir_list, np.zeros((sysm.no, sysm.nv)), g2)[1]).max() < 1e-12
     with pytest.raises(rteom.RteomError):
         P.spectral(np.linspace(-1, 1, 5), 0.1)      # no core hole
+
+
+def test_ground_state_same_spin_blocks_stay_antisymmetric():
+    """Regression: the tiny workload's ground state takes 174 Jacobi iterations; without the
+    per-iteration antisymmetrisation of the same-spin blocks their symmetric part grew from
+    rounding level to NaN before convergence.  Energy and iteration count match the oracle."""
+    from oracle import groundstate
+    eps, chol = draw_system(Shape(4, 16, 48), cfg=0)
+    sysm = reference.closed_shell_reference(eps, chol, 4, 4)
+    e_ref, _, _, it_ref = groundstate.solve(sysm, tol=1e-11)
+    P = rteom.Propagator(eps, chol, 4, 4, -1, 0, lib_path=LIB)
+    e, it = P.ground_state(tol=1e-11, max_iter=400)
+    assert it == it_ref
+    assert abs(e - e_ref) < 1e-11 * abs(e_ref)
+    _, t2 = P.get_amplitudes()
+    assert np.abs(t2[0] + t2[0].transpose(1, 0, 2, 3)).max() < 1e-15

@@ -220,11 +220,13 @@ def test_checkpoint_restart_with_graph_replay():
     assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
 
 
-@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-6, 1e-8), ("bf16x3", 1e-4, 1e-6)])
+@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-5, 1e-6), ("bf16x3", 1e-4, 1e-5)])
 def test_ground_state_ccsd(prec, tol, solve_tol):
     """E_N^corr of the tiny workload's N-electron determinant (core_orb = -1) by
     rteom_ground_state against the oracle's Jacobi solution (relative error bound per
-    precision; float64 also takes the same number of iterations)."""
+    precision; float64 also takes the same number of iterations).  The reduced-precision
+    contractions put a floor of ~1e-7 (float32) and ~1e-6 (bf16x3) under the change of an
+    iterate, so those iterations stop at 1e-6 and 1e-5."""
     from oracle import groundstate
     eps, chol = draw_system(TINY, cfg=0)
     sysm = reference.closed_shell_reference(eps, chol, 4, 4)

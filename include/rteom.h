@@ -86,7 +86,12 @@ typedef struct {
                               candidate tile shape is timed on it and the fastest is kept for
                               the context (results are bit-identical for every tile shape);
                               0: tile shape from a work-per-byte rule */
-  int32_t reserved1;       /* must be 0 */
+  int32_t fp_anderson;     /* 0..8: history depth m of Anderson acceleration of the
+                              tolerance-driven fixed point (fp_fixed_iters = 0) and of
+                              rteom_ground_state: each pass mixes the last m results
+                              G(x_j) with the weights (sum 1) that minimise the norm of
+                              the mixed G(x_j) - x_j; 0 = plain iteration.  Costs 2 m
+                              amplitude sets of workspace. */
 } rteom_options;
 
 /* Fill *opt with defaults: FP64, plain map, tolerance 1e-10, 50 passes,

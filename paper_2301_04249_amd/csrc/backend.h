@@ -154,6 +154,9 @@ class Backend {
   // *step = k + 1.  c_hist, e_hist: device (re, im) pairs; e_next: device pair.
   virtual void cumulant_append(double* c_hist, double* e_hist, const double* e_next,
                                int64_t* step, double h) = 0;
+  // *out = sum_k a[k] b[k] (device pointers), summed in a fixed order; part is
+  // scratch of energy_partials() doubles.
+  virtual void dot(const double* a, const double* b, int64_t n, double* part, double* out) = 0;
   // Spectral function from the cumulant history (all pointers device memory):
   // c_hist [n][2] C(t_k), times [n], omega [n_w] -> a_out [n_w] A(omega),
   // qp_out [2] = (refined position of the largest A, A at the grid maximum);

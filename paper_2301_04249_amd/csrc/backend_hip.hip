@@ -995,6 +995,25 @@ __global__ __launch_bounds__(64) void energy_pass2(EnArgs e, int nparts) {
   if (threadIdx.x == 0) { e.out[0] = ar; e.out[1] = ai; }
 }
 
+// sum_k a[k] b[k] in a fixed order: kEnergyBlocks block partials, then one wave.
+__global__ __launch_bounds__(256) void dot_pass1(const double* a, const double* b, int64_t n, double* part) {
+  __shared__ double sr[4];
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) acc += a[k] * b[k];
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) sr[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = sr[0] + sr[1] + sr[2] + sr[3];
+}
+
+__global__ __launch_bounds__(64) void dot_pass2(const double* part, int nparts, double* out) {
+  double acc = 0.0;
+  for (int k = threadIdx.x; k < nparts; k += 64) acc += part[k];
+  acc = wave_sum(acc);
+  if (threadIdx.x == 0) out[0] = acc;
+}
+
 __global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t* step, double h) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t k = *step;
@@ -1589,6 +1608,15 @@ class HipBackend : public Backend {
     begin();
     cumulant_kernel<<<1, 64, 0, stream_>>>(c, e, en, step, h);
     launched("cumulant");
+    end();
+  }
+
+  void dot(const double* a, const double* b, int64_t n, double* part, double* out) override {
+    begin();
+    dot_pass1<<<kEnergyBlocks, 256, 0, stream_>>>(a, b, n, part);
+    launched("dot_pass1");
+    dot_pass2<<<1, 64, 0, stream_>>>(part, kEnergyBlocks, out);
+    launched("dot_pass2");
     end();
   }
 

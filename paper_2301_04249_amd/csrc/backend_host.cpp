@@ -199,6 +199,12 @@ class HostBackend : public Backend {
     e.e_out[1] = ei;
   }
 
+  void dot(const double* a, const double* b, int64_t n, double*, double* out) override {
+    double acc = 0.0;
+    for (int64_t k = 0; k < n; ++k) acc += a[k] * b[k];
+    *out = acc;
+  }
+
   void spectral(const double* c, const double* t, int64_t n, double shift, double eta, const double* omega,
                 int64_t n_w, double* wg, double* a, double* qp) override {
     if (n < 1 || n_w < 1) return;

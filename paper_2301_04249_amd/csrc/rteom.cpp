@@ -22,6 +22,7 @@
 //   timeline tensors.  C(t) accumulates i E(T) with the same trapezoid weights.
 #include <algorithm>
 #include <cmath>
+#include <complex>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -72,6 +73,12 @@ struct Context {
   double* epart = nullptr;
   double* e_hist = nullptr;  // [(max_steps+1)][2]
   double* e_next = nullptr;  // E(T_{n+1}) of the step in flight
+  // Anderson acceleration of the tolerance-driven fixed points: ring of the last
+  // am iterates x_j and differences f_j = G(x_j) - x_j, their Gram matrix (host)
+  int am = 0, a_count = 0, a_head = 0;
+  std::vector<double*> a_x, a_f;
+  std::vector<double> a_gram;
+  double* a_dot = nullptr;
   int64_t* dstep = nullptr;  // steps taken, on the device (indexes the histories)
   void* step_graph = nullptr;
   double graph_dt = 0.0;
@@ -182,6 +189,15 @@ struct Context {
     c_hist = take(2 * (opt.max_steps + 1));
     e_next = take(2);
     dstep = reinterpret_cast<int64_t*>(take(1));
+    am = opt.fp_anderson;
+    a_x.clear();
+    a_f.clear();
+    for (int j = 0; j < am; ++j) {
+      a_x.push_back(take(2 * ns));
+      a_f.push_back(take(2 * ns));
+    }
+    a_gram.assign(2 * (size_t)am * am, 0.0);
+    a_dot = take(1);
 
     // Cholesky blocks in the extended ordering (host reorder, then copy)
     if (!dry) {
@@ -581,6 +597,88 @@ struct Context {
     return opt.fp_fixed_iters;
   }
 
+  // ---- Anderson acceleration (type II, Pulay/DIIS form) of a fixed point x = G(x):
+  // with f_j = G(x_j) - x_j over the last c <= am iterates, the next iterate is
+  // sum_j a_j G(x_j) with the complex a_j (sum 1) that minimise |sum_j a_j f_j|_2.
+  // Complex weights: the error modes of the time-step map rotate in the complex
+  // plane (the i dt/2 factor), which real weights cannot cancel.
+  View flat(double* set) const { return make_view(set, nullptr, {2 * lay.size()}); }
+  View cplx(double* set) const { return make_view(set, set + lay.size(), {lay.size()}); }
+  void anderson_reset() { a_count = 0; a_head = 0; }
+  // before G is applied to X: keep x
+  void anderson_keep_x() { be->d2d(a_x[a_head], X, sizeof(double) * 2 * lay.size()); }
+  double dot(const double* a, const double* b, int64_t n) {
+    double d = 0.0;
+    be->dot(a, b, n, epart, a_dot);
+    be->d2h(&d, a_dot, sizeof(double));
+    return d;
+  }
+  // after X = G(x): record f = G(x) - x and replace X by the mixed iterate
+  void anderson_mix() {
+    typedef std::complex<double> cd;
+    const int h = a_head;
+    const int64_t ns = lay.size();
+    eng.set_phase(kPhaseMove);
+    eng.add(flat(a_f[h]), flat(X), 1.0, 0.0, 0);
+    eng.add(flat(a_f[h]), flat(a_x[h]), -1.0, 0.0, 1);
+    a_count = std::min(a_count + 1, am);
+    std::vector<int> slots;   // oldest first
+    for (int k = a_count - 1; k >= 0; --k) slots.push_back((h - k + am) % am);
+    for (int j : slots) {
+      // <f_h, f_j> = sum conj(f_h) f_j
+      const double re = dot(a_f[h], a_f[j], 2 * ns);
+      const double im = j == h ? 0.0 : dot(a_f[h], a_f[j] + ns, ns) - dot(a_f[h] + ns, a_f[j], ns);
+      a_gram[2 * ((size_t)h * am + j)] = re;
+      a_gram[2 * ((size_t)h * am + j) + 1] = im;
+      a_gram[2 * ((size_t)j * am + h)] = re;
+      a_gram[2 * ((size_t)j * am + h) + 1] = -im;
+    }
+    a_head = (h + 1) % am;
+    const int c = (int)slots.size();
+    if (c < 2) return;   // X = G(x) as it stands
+    // [B 1; 1^T 0] [a; l] = [0; 1], B_ij = <f_i, f_j>, by elimination with pivoting
+    const int n1 = c + 1;
+    std::vector<cd> A((size_t)n1 * n1, cd(0.0)), rhs(n1, cd(0.0));
+    double scale = 0.0;
+    for (int i = 0; i < c; ++i) scale = std::max(scale, a_gram[2 * ((size_t)slots[i] * am + slots[i])]);
+    if (!(scale > 0.0)) return;
+    for (int i = 0; i < c; ++i) {
+      for (int j = 0; j < c; ++j) {
+        const size_t g = 2 * ((size_t)slots[i] * am + slots[j]);
+        A[(size_t)i * n1 + j] = cd(a_gram[g], a_gram[g + 1]) / scale;
+      }
+      A[(size_t)i * n1 + i] *= 1.0 + 1e-12;
+      A[(size_t)i * n1 + c] = A[(size_t)c * n1 + i] = cd(1.0);
+    }
+    rhs[c] = cd(1.0);
+    for (int col = 0; col < n1; ++col) {
+      int piv = col;
+      for (int r = col + 1; r < n1; ++r)
+        if (std::abs(A[(size_t)r * n1 + col]) > std::abs(A[(size_t)piv * n1 + col])) piv = r;
+      if (std::abs(A[(size_t)piv * n1 + col]) < 1e-300) return;   // degenerate: keep G(x)
+      for (int k = 0; k < n1; ++k) std::swap(A[(size_t)col * n1 + k], A[(size_t)piv * n1 + k]);
+      std::swap(rhs[col], rhs[piv]);
+      for (int r = col + 1; r < n1; ++r) {
+        const cd fct = A[(size_t)r * n1 + col] / A[(size_t)col * n1 + col];
+        for (int k = col; k < n1; ++k) A[(size_t)r * n1 + k] -= fct * A[(size_t)col * n1 + k];
+        rhs[r] -= fct * rhs[col];
+      }
+    }
+    std::vector<cd> a(n1, cd(0.0));
+    for (int r = n1 - 1; r >= 0; --r) {
+      cd v = rhs[r];
+      for (int k = r + 1; k < n1; ++k) v -= A[(size_t)r * n1 + k] * a[k];
+      a[r] = v / A[(size_t)r * n1 + r];
+    }
+    for (int i = 0; i < c; ++i)
+      if (!std::isfinite(a[i].real()) || !std::isfinite(a[i].imag())) return;
+    // X = sum_j a_j (x_j + f_j), complex a_j on planar complex sets
+    for (int i = 0; i < c; ++i) {
+      eng.add(cplx(X), cplx(a_x[slots[i]]), a[i].real(), a[i].imag(), i == 0 ? 0 : 1);
+      eng.add(cplx(X), cplx(a_f[slots[i]]), a[i].real(), a[i].imag(), 1);
+    }
+  }
+
   // Same-spin doubles are stored in full; keep them antisymmetric in a Jacobi
   // iteration, whose map amplifies their symmetric part (which the equations never
   // constrain) from rounding level by ~0.17 e-folds per iteration otherwise.
@@ -604,8 +702,10 @@ struct Context {
     be->fill(X, 2 * lay.size(), 0.0);
     UpdateOp u = update_op(false);
     u.mode = 2;
+    anderson_reset();
     for (int it = 1; it <= max_iter; ++it) {
       residual(X, R);
+      if (am > 0) anderson_keep_x();
       be->set_phase(kPhaseUpdate);
       be->fill(delta, 1, 0.0);
       be->update(u);
@@ -619,6 +719,7 @@ struct Context {
         be->d2h(e_out, e_next, 2 * sizeof(double));
         return it;
       }
+      if (am > 0) anderson_mix();
     }
     throw Error(RTEOM_ERR_NOCONV, "ground-state CCSD not converged in " + std::to_string(max_iter) + " iterations");
   }
@@ -626,7 +727,10 @@ struct Context {
   int enqueue_step(double dt) {
     UpdateOp u0 = update_op(true);
     u0.h = 0.5 * dt;
+    const bool accel = am > 0 && opt.fp_fixed_iters == 0;   // tolerance-driven passes only
+    if (accel) anderson_reset();
     residual(X, R);
+    if (accel) anderson_keep_x();
     be->set_phase(kPhaseUpdate);
     be->fill(delta, 1, 0.0);
     be->update(u0);
@@ -649,7 +753,9 @@ struct Context {
         if (passes >= opt.fp_max_iter)
           throw Error(RTEOM_ERR_NOCONV, "fixed point not converged after " + std::to_string(passes) +
                                             " passes (last change " + std::to_string(d) + ")");
+        if (accel) anderson_mix();
         residual(X, R);
+        if (accel) anderson_keep_x();
         be->set_phase(kPhaseUpdate);
         be->fill(delta, 1, 0.0);
         be->update(u);
@@ -711,7 +817,8 @@ bool valid_options(const rteom_options* o, std::string* m) {
   if (o->fp_fixed_iters < 0 || o->fp_max_iter < 1) { *m = "bad pass counts"; return false; }
   if (!(o->fp_tol > 0.0)) { *m = "fp_tol must be positive"; return false; }
   if (o->max_steps < 1) { *m = "max_steps must be >= 1"; return false; }
-  if (o->tune < 0 || o->tune > 1 || o->reserved1 != 0) { *m = "tune must be 0 or 1, reserved1 0"; return false; }
+  if (o->tune < 0 || o->tune > 1) { *m = "tune must be 0 or 1"; return false; }
+  if (o->fp_anderson < 0 || o->fp_anderson > 8) { *m = "fp_anderson must be in 0..8"; return false; }
   return true;
 }
 

@@ -50,7 +50,7 @@ class Options(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_size_t),
         ("tune", ctypes.c_int32),
-        ("reserved1", ctypes.c_int32),
+        ("fp_anderson", ctypes.c_int32),
     ]
 
 
@@ -116,7 +116,7 @@ class Propagator:
 
     def __init__(self, eps, chol, n_occ_a, n_occ_b, core_orb=0, core_spin=1, prec="fp64", fp_map=0,
                  fixed_iters=0, max_iter=50, tol=1e-10, include_ft1=True, max_steps=100000,
-                 stream=None, workspace=None, graph=False, tune=True, lib_path=LIB_PATH):
+                 stream=None, workspace=None, graph=False, tune=True, anderson=0, lib_path=LIB_PATH):
         self.lib = load(lib_path)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         chol = np.ascontiguousarray(chol, dtype=np.float64)
@@ -133,6 +133,7 @@ class Propagator:
         opt.max_steps = int(max_steps)
         opt.graph = 1 if graph else 0
         opt.tune = 1 if tune else 0
+        opt.fp_anderson = int(anderson)
         opt.stream = stream
         self._ws = None
         if workspace == "torch":

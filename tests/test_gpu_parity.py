@@ -240,6 +240,27 @@ def test_ground_state_ccsd(prec, tol, solve_tol):
         assert it == it_ref
 
 
+def test_anderson_acceleration_on_device():
+    """fp_anderson = 3 on the device: ground state in far fewer iterations than the plain
+    Jacobi solve (same E_corr), tolerance-driven steps with fewer passes (same C(t))."""
+    from oracle import groundstate
+    tr, _, _ = _tiny_reference()
+    eps, chol = draw_system(TINY, cfg=0)
+    sysm = reference.closed_shell_reference(eps, chol, 4, 4)
+    e_ref, _, _, it_ref = groundstate.solve(sysm, tol=1e-11)
+    e, it = _prop(eps, chol, 4, 4, -1, 0, anderson=3).ground_state(tol=1e-11, max_iter=400)
+    print(f"ground state: {it} accelerated iterations vs {it_ref} Jacobi, E rel err {abs(e - e_ref) / abs(e_ref):.1e}")
+    assert it < it_ref / 4 and abs(e - e_ref) < 1e-9 * abs(e_ref)
+    ref = propagate.propagate(reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1), 0.025, 20, tol=1e-13)
+    passes = []
+    for m in (0, 3):
+        P = _prop(eps, chol, 4, 4, 0, 1, tol=1e-10, anderson=m)
+        passes.append(int(np.sum(P.step(0.025, 20))))
+        assert np.abs(P.cumulant()[1] - ref.cumulant).max() < 1e-9
+    print(f"20 steps at tol 1e-10: {passes[0]} passes plain, {passes[1]} with Anderson (m = 3)")
+    assert passes[1] < 0.8 * passes[0]
+
+
 def test_batch_of_uneven_systems_matches_sequential():
     """Three uneven core-hole systems in one graph launch per step equal their separate runs."""
     shapes = [Shape(3, 9, 20), Shape(4, 14, 40), Shape(5, 11, 30)]

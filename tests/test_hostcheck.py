@@ -192,3 +192,26 @@ def test_ground_state_same_spin_blocks_stay_antisymmetric():
     assert abs(e - e_ref) < 1e-11 * abs(e_ref)
     _, t2 = P.get_amplitudes()
     assert np.abs(t2[0] + t2[0].transpose(1, 0, 2, 3)).max() < 1e-15
+
+
+def test_anderson_acceleration():
+    """fp_anderson = 3: the ground-state Jacobi solve reaches the oracle's E_corr in far fewer
+    iterations, and tolerance-driven time steps need fewer passes for the same C(t)."""
+    from oracle import groundstate
+    eps, chol = draw_system(Shape(4, 16, 48), cfg=0)
+    sysm = reference.closed_shell_reference(eps, chol, 4, 4)
+    e_ref = groundstate.solve(sysm, tol=1e-12)[0]
+    P = rteom.Propagator(eps, chol, 4, 4, -1, 0, anderson=3, lib_path=LIB)
+    e, it = P.ground_state(tol=1e-11, max_iter=400)
+    assert it < 40
+    assert abs(e - e_ref) < 1e-9 * abs(e_ref)
+    sysn = reference.n_minus_one_reference(eps, chol, 4, 4, 0, 1)
+    tr = propagate.propagate(sysn, 0.025, 8, tol=1e-13)
+    passes = []
+    for m in (0, 3):
+        Q = rteom.Propagator(eps, chol, 4, 4, 0, 1, tol=1e-10, anderson=m, lib_path=LIB)
+        passes.append(int(np.sum(Q.step(0.025, 8))))
+        assert np.abs(Q.cumulant()[1] - tr.cumulant).max() < 1e-9
+    assert passes[1] < 0.8 * passes[0]
+    with pytest.raises(rteom.RteomError):
+        rteom.Propagator(eps, chol, 4, 4, 0, 1, anderson=9, lib_path=LIB)

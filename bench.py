@@ -32,8 +32,6 @@ KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands 
 # summaries (with the commands) are under profiles/.  Only workloads whose
 # ladder kernel has been counted since its last change are listed.
 TRAFFIC = {
-    # profiles/gemm_mfma_ladder_esca_fp64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 per launch
-    ("esca", "fp64"): 5.021e12,
 }
 
 DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",
@@ -146,10 +144,10 @@ def run_batch(args, work):
     lad_ms = lad_flop_total = 0.0
     lad_ops = 0
     for q in qs:
-        ms, ops, fl = q.phase_stats("ladder")
+        ms, ops, fl = q.phase_stats("ladder")   # fl: the ladder's flops per residual
         lad_ms += ms
         lad_ops += ops
-        lad_flop_total += fl * ops
+        lad_flop_total += fl * passes * args.steps
     for q in qs:
         q.close()
     del qs
@@ -280,7 +278,9 @@ def main(argv=None):
     if not np.all(np.isfinite(c)):
         print("bench.py: non-finite C(t)", file=sys.stderr)
         return 3
-    achieved = lad_flops * lad_ops / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
+    # the ladder phase: two launches per residual (alpha-beta block, same-spin pairs)
+    lad_total = lad_flops * n_res
+    achieved = lad_total / (lad_ms * 1e-3) / 1e12 if lad_ms > 0 else 0.0
     avg_ms = lad_ms / lad_ops if lad_ops else None
     traffic = TRAFFIC.get((args.workload, args.prec))
     peak = PEAK_TFLOPS[args.prec]
@@ -304,11 +304,12 @@ def main(argv=None):
         "dtype": DTYPE[args.prec],
         "data": "synthetic (seeded eps and Cholesky vectors of the stated shape)",
         "config": config,
-        "roofline": {"kernel": KERNEL_NAME[args.prec] + " particle-particle ladder (3 spin blocks in one launch)",
+        "roofline": {"kernel": KERNEL_NAME[args.prec] + " particle-particle ladder (alpha-beta block in full "
+                               "storage and both same-spin blocks in pair storage: two launches per residual)",
                      "bound": "mfma", "achieved": round(achieved, 4), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 5),
                      "traffic": traffic,
-                     "launches": lad_ops, "flops_per_launch": lad_flops,
+                     "launches": lad_ops, "flops_per_launch": lad_total / lad_ops if lad_ops else None,
                      "avg_launch_ms": round(avg_ms, 5) if avg_ms else None,
                      "timing": "HIP events on the engine stream around each ladder launch, " + (
                          "in a second timed region of the same steps with direct launches" if mode == "graph"

@@ -98,6 +98,27 @@ struct UpdateOp {
   double* delta = nullptr;  // device double, max-reduced (caller zeroes it)
 };
 
+// Antisymmetric pair storage of same-spin blocks.  x holds nblk blocks (x_bs
+// doubles apart) of shape [n1][n1][rest]; rest is [n2][n2] (pair2 = 1) or n2
+// plain elements (pair2 = 0).  y holds the packed form [np1][nq] per block (y_bs
+// apart) over index pairs p = (i < j) and, with pair2, q = (a < b), both in
+// lexicographic order: np1 = n1 (n1 - 1) / 2, nq = n2 (n2 - 1) / 2 or n2.
+//   pack   (mode 0): y[p][q] = alpha (x[i][j][c] - anti x[j][i][c]), c = (a, b) or q
+//   unpack (mode 1): x[i][j][c] = alpha s y[p][q] + beta x[i][j][c] for i != j (and
+//                    a != b), s = -1 per swapped pair; elements with i == j (or
+//                    a == b) become beta x.
+// x and y are planar complex when x_im / y_im are set (both or neither).
+struct PairOp {
+  int64_t n1 = 0, n2 = 0, nblk = 1;
+  int pair2 = 1;
+  double* x_re = nullptr; double* x_im = nullptr; int64_t x_bs = 0;
+  double* y_re = nullptr; double* y_im = nullptr; int64_t y_bs = 0;
+  double alpha = 1.0;
+  int anti = 0;
+  int mode = 0;
+  int beta = 0;
+};
+
 // E(T) = sum f_ia t_ia + 1/4 sum <ij||ab> t_ijab + 1/2 sum <ij||ab> t_ia t_jb in
 // spin-blocked form; writes (re, im) to e_out (device).
 struct EnergyOp {
@@ -148,6 +169,7 @@ class Backend {
   virtual void fill(double* p, int64_t n, double v) = 0;
   virtual void gemm(const GemmOp& op) = 0;
   virtual void permute(const PermOp& op) = 0;
+  virtual void pairs(const PairOp& op) = 0;
   virtual void update(const UpdateOp& op) = 0;
   virtual void energy(const EnergyOp& op) = 0;
   // With k = *step (device): C[k+1] = C[k] + i h (E[k] + e_next), E[k+1] = e_next,

@@ -54,6 +54,7 @@ struct GemmArgs {
   const unsigned short* sa[4];
   const unsigned short* sb[4];
   int64_t sld, sab, sbb;      // row length and batch strides (0: one matrix for all batch entries)
+  int64_t aext, bext;         // elements spanned by A and B from ar / br (all batch entries)
 };
 
 // Output tile of work-group `bid`.  Work-groups are dispatched round-robin over
@@ -75,6 +76,25 @@ __device__ inline void tile_coords(const GemmArgs& g, int64_t bid, int64_t& tm, 
   const int64_t f = band * kGroup + within % width, o = within / width;
   if (g.m_fast) { tm = f; tn = o; }
   else          { tn = f; tm = o; }
+}
+
+// Buffer resource over [p, p + n) elements (n clamped to the 31-bit byte range);
+// loads outside it return zero.  Raw (unswizzled, stride 0) resource whose last
+// descriptor word selects the 32-bit data format of gfx9 buffer loads.
+template <typename S>
+__device__ inline __amdgpu_buffer_rsrc_t window(const S* p, int64_t n) {
+  const int64_t bytes = n <= 0 ? 0 : (n * (int64_t)sizeof(S) > 0x7fffffffLL ? 0x7fffffffLL : n * (int64_t)sizeof(S));
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<S*>(p), (short)0, (int)bytes, 0x00020000);
+}
+template <typename S>
+__device__ inline S ldbuf(__amdgpu_buffer_rsrc_t r, int voff, int soff);
+template <>
+__device__ inline double ldbuf<double>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+}
+template <>
+__device__ inline float ldbuf<float>(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
 }
 
 // Operand tiles are staged k-major in LDS ([BK][BM] for A, [BK][BN] for B) so
@@ -151,14 +171,17 @@ __global__ __launch_bounds__(64 * GM * GN)
     b0 = 0;
     bstep = 1;
   }
-  const int64_t a_rs = AMS * g.asm_ + AKS * g.ask, b_rs = BKS * g.bsk + BNS * g.bsn;
-  const int64_t a_off = (m0 + am0) * g.asm_ + ak0 * g.ask, b_off = (n0 + bn0) * g.bsn + bk0 * g.bsk;
-  const int64_t a_mrem = g.M - m0 - am0, b_nrem = g.N - n0 - bn0;   // rows / columns left
+  // Operands are read through buffer resources whose base is the tile's origin at
+  // the current k (scalar registers); a thread adds its own 32-bit byte offset and
+  // a uniform offset per staged element.  Reads past the operand's extent return
+  // zero; rows and columns past M and N hold values that only reach output
+  // elements that are never stored, and the k positions past the end of the sum
+  // are zeroed explicitly in the last K tile.
+  const int a_rs = (int)((AMS * g.asm_ + AKS * g.ask) * (int64_t)sizeof(S));
+  const int b_rs = (int)((BKS * g.bsk + BNS * g.bsn) * (int64_t)sizeof(S));
+  const int a_thr = (int)((am0 * g.asm_ + ak0 * g.ask) * (int64_t)sizeof(S));
+  const int b_thr = (int)((bn0 * g.bsn + bk0 * g.bsk) * (int64_t)sizeof(S));
   for (int64_t b = b0; b < g.batch; b += bstep) {
-    const S* Ar = reinterpret_cast<const S*>(g.ar) + b * g.asb;
-    const S* Ai = AC ? reinterpret_cast<const S*>(g.ai) + b * g.asb : nullptr;
-    const S* Br = reinterpret_cast<const S*>(g.br) + b * g.bsb;
-    const S* Bi = BC ? reinterpret_cast<const S*>(g.bi) + b * g.bsb : nullptr;
     acc_t accr[WM][WN], acci[WM][WN];
 #pragma unroll
     for (int x = 0; x < WM; ++x)
@@ -168,27 +191,31 @@ __global__ __launch_bounds__(64 * GM * GN)
         acci[x][y] = acc_t{0, 0, 0, 0};
       }
     S pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
+    const int64_t a_org = b * g.asb + m0 * g.asm_, b_org = b * g.bsb + n0 * g.bsn;
     auto fetch = [&](int64_t k0) {
-      const int64_t ka = kend - k0 - ak0, kb = kend - k0 - bk0;   // k positions left
+      const int64_t ao = a_org + k0 * g.ask, bo = b_org + k0 * g.bsk;
+      const auto rar = window<S>(reinterpret_cast<const S*>(g.ar) + ao, g.aext - ao);
+      const auto rai = window<S>(AC ? reinterpret_cast<const S*>(g.ai) + ao : nullptr, g.aext - ao);
+      const auto rbr = window<S>(reinterpret_cast<const S*>(g.br) + bo, g.bext - bo);
+      const auto rbi = window<S>(BC ? reinterpret_cast<const S*>(g.bi) + bo : nullptr, g.bext - bo);
 #pragma unroll
       for (int r = 0; r < NA; ++r) {
-        pa_r[r] = 0;
-        pa_i[r] = 0;
-        if (r * AMS < a_mrem && r * AKS < ka) {
-          const int64_t o = a_off + k0 * g.ask + r * a_rs;
-          pa_r[r] = Ar[o];
-          if (AC) pa_i[r] = Ai[o];
-        }
+        pa_r[r] = ldbuf<S>(rar, a_thr, r * a_rs);
+        pa_i[r] = AC ? ldbuf<S>(rai, a_thr, r * a_rs) : (S)0;
       }
 #pragma unroll
       for (int r = 0; r < NB; ++r) {
-        pb_r[r] = 0;
-        pb_i[r] = 0;
-        if (r * BNS < b_nrem && r * BKS < kb) {
-          const int64_t o = b_off + k0 * g.bsk + r * b_rs;
-          pb_r[r] = Br[o];
-          if (BC) pb_i[r] = Bi[o];
-        }
+        pb_r[r] = ldbuf<S>(rbr, b_thr, r * b_rs);
+        pb_i[r] = BC ? ldbuf<S>(rbi, b_thr, r * b_rs) : (S)0;
+      }
+      if (k0 + BK > kend) {   // last, partial K tile
+        const int64_t ka = kend - k0 - ak0, kb = kend - k0 - bk0;
+#pragma unroll
+        for (int r = 0; r < NA; ++r)
+          if (!(r * AKS < ka)) { pa_r[r] = 0; pa_i[r] = 0; }
+#pragma unroll
+        for (int r = 0; r < NB; ++r)
+          if (!(r * BKS < kb)) { pb_r[r] = 0; pb_i[r] = 0; }
       }
     };
     auto stage = [&](int buf) {
@@ -753,6 +780,91 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
     }
     p.orr[oo] = vr;
     if (p.oi) p.oi[oo] = vi;
+  }
+}
+
+// Antisymmetric pair storage (PairOp): pairs p = (i < j) of n in lexicographic
+// order start at pair_start(i, n) = i (2n - i - 1) / 2.
+struct PairArgs {
+  int64_t n1, n2, np1, nq, rows;
+  int pair2, anti, beta;
+  double* xr; double* xi; int64_t xbs;
+  double* yr; double* yi; int64_t ybs;
+  double alpha;
+};
+
+__device__ inline int64_t pair_start(int64_t i, int64_t n) { return i * (2 * n - i - 1) / 2; }
+
+// (i, j) of pair p: the square-root estimate of i, corrected by exact integer tests
+__device__ inline void pair_of(int64_t p, int64_t n, int64_t& i, int64_t& j) {
+  const double b = 2.0 * (double)n - 1.0;
+  int64_t k = (int64_t)floor(0.5 * (b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))));
+  k = k < 0 ? 0 : (k > n - 2 ? n - 2 : k);
+  while (k > 0 && pair_start(k, n) > p) --k;
+  while (k < n - 2 && pair_start(k + 1, n) <= p) ++k;
+  i = k;
+  j = p - pair_start(k, n) + k + 1;
+}
+
+// One packed row per iteration: (block, p, a) with pair2, else (block, p).
+__global__ __launch_bounds__(256) void pair_pack(PairArgs g) {
+  const int64_t rest = g.pair2 ? g.n2 * g.n2 : g.n2;
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    int64_t r = row, a = 0;
+    if (g.pair2) { a = r % g.n2; r /= g.n2; }
+    const int64_t p = r % g.np1, blk = r / g.np1;
+    int64_t i, j;
+    pair_of(p, g.n1, i, j);
+    const int64_t xij = blk * g.xbs + (i * g.n1 + j) * rest, xji = blk * g.xbs + (j * g.n1 + i) * rest;
+    const int64_t yo = blk * g.ybs + p * g.nq + (g.pair2 ? pair_start(a, g.n2) - a - 1 : 0);
+    const int64_t c0 = g.pair2 ? a * g.n2 : 0;
+    const int64_t lo = g.pair2 ? a + 1 : 0;
+    for (int64_t b = lo + threadIdx.x; b < g.n2; b += blockDim.x) {
+      const int64_t c = c0 + b;
+      double vr = g.xr[xij + c], vi = g.xi ? g.xi[xij + c] : 0.0;
+      if (g.anti) {
+        vr -= g.xr[xji + c];
+        if (g.xi) vi -= g.xi[xji + c];
+      }
+      g.yr[yo + b] = g.alpha * vr;
+      if (g.yi) g.yi[yo + b] = g.alpha * vi;
+    }
+  }
+}
+
+// One full row per iteration: (block, i, j, a) with pair2, else (block, i, j).
+__global__ __launch_bounds__(256) void pair_unpack(PairArgs g) {
+  const int64_t rest = g.pair2 ? g.n2 * g.n2 : g.n2;
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    int64_t r = row, a = 0;
+    if (g.pair2) { a = r % g.n2; r /= g.n2; }
+    const int64_t j = r % g.n1;
+    r /= g.n1;
+    const int64_t i = r % g.n1, blk = r / g.n1;
+    const int64_t xo = blk * g.xbs + (i * g.n1 + j) * rest + (g.pair2 ? a * g.n2 : 0);
+    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
+    const int64_t yo = blk * g.ybs + (pair_start(lo, g.n1) + hi - lo - 1) * g.nq;
+    const double sij = i < j ? 1.0 : -1.0;
+    for (int64_t b = threadIdx.x; b < g.n2; b += blockDim.x) {
+      double vr = 0.0, vi = 0.0;
+      if (i != j && (!g.pair2 || a != b)) {
+        int64_t q = b;
+        double sg = sij;
+        if (g.pair2) {
+          const int64_t qa = a < b ? a : b, qb = a < b ? b : a;
+          q = pair_start(qa, g.n2) + qb - qa - 1;
+          if (b < a) sg = -sg;
+        }
+        vr = g.alpha * sg * g.yr[yo + q];
+        if (g.yi) vi = g.alpha * sg * g.yi[yo + q];
+      }
+      if (g.beta) {
+        vr += g.xr[xo + b];
+        if (g.xi) vi += g.xi[xo + b];
+      }
+      g.xr[xo + b] = vr;
+      if (g.xi) g.xi[xo + b] = vi;
+    }
   }
 }
 
@@ -1345,6 +1457,8 @@ class HipBackend : public Backend {
     g.cr = op.c_re; g.ci = op.c_im; g.csm = op.c_sm; g.csn = op.c_sn; g.csb = op.c_sb;
     g.alpha = op.alpha;
     g.beta = op.beta;
+    g.aext = 1 + (op.M - 1) * op.a_sm + (op.K - 1) * op.a_sk + (op.a_sb ? (op.batch - 1) * op.a_sb : 0);
+    g.bext = 1 + (op.N - 1) * op.b_sn + (op.K - 1) * op.b_sk + (op.b_sb ? (op.batch - 1) * op.b_sb : 0);
     g.tiles_m = (op.M + BM - 1) / BM;
     g.tiles_n = (op.N + BN - 1) / BN;
     g.splitk = 1;
@@ -1378,6 +1492,11 @@ class HipBackend : public Backend {
     if (presplit) {
       if (op.prec == 2) split_operands(op, g, ac, bc);
       else f32_operands(op, g, ac, bc);
+    }
+    if (!(presplit && op.prec == 2) && !windows_fit(g, op.prec == 0 || !presplit ? 8 : 4)) {
+      set_err("gemm: an operand tile spans more than 2 GiB");
+      end();
+      return;
     }
     const int v = choose_tile(op, g, ac, bc, akc, bkc, presplit);
     if (v < 0) { end(); return; }
@@ -1447,6 +1566,18 @@ class HipBackend : public Backend {
     g.bi = reinterpret_cast<const double*>(pl[3]);
     g.asm_ = ld; g.ask = 1; g.asb = op.a_sb ? op.M * ld : 0;
     g.bsn = ld; g.bsk = 1; g.bsb = op.b_sb ? op.N * ld : 0;
+    g.aext = nba * op.M * ld;
+    g.bext = nbb * op.N * ld;
+  }
+
+  // The product kernels address one K tile of each operand through a buffer
+  // resource with 32-bit offsets: the tile's extent must stay below 2 GiB.
+  // (checked for the largest tile, 128 x 128, so that every candidate fits)
+  static bool windows_fit(const GemmArgs& g, int64_t es) {
+    const int64_t lim = int64_t(1) << 31;
+    const int64_t wa = (127 * std::llabs(g.asm_) + (BK - 1) * std::llabs(g.ask) + 1) * es;
+    const int64_t wb = (127 * std::llabs(g.bsn) + (BK - 1) * std::llabs(g.bsk) + 1) * es;
+    return wa < lim && wb < lim;
   }
 
   void set_tuning(int on) override { tuning_ = on != 0; }
@@ -1572,6 +1703,26 @@ class HipBackend : public Backend {
       permute_kernel<<<grid_for(p.total), 256, 0, stream_>>>(p);
       launched("permute");
     }
+    end();
+  }
+
+  void pairs(const PairOp& op) override {
+    PairArgs g;
+    g.n1 = op.n1; g.n2 = op.n2; g.pair2 = op.pair2; g.anti = op.anti; g.beta = op.beta;
+    g.np1 = op.n1 * (op.n1 - 1) / 2;
+    g.nq = op.pair2 ? op.n2 * (op.n2 - 1) / 2 : op.n2;
+    g.xr = op.x_re; g.xi = op.x_im; g.xbs = op.x_bs;
+    g.yr = op.y_re; g.yi = op.y_im; g.ybs = op.y_bs;
+    g.alpha = op.alpha;
+    g.rows = op.mode == 0 ? op.nblk * g.np1 * (op.pair2 ? op.n2 : 1)
+                          : op.nblk * op.n1 * op.n1 * (op.pair2 ? op.n2 : 1);
+    if (g.rows <= 0 || op.n2 <= 0) return;
+    if (op.mode == 0 && op.n1 < 2) return;
+    begin();
+    const unsigned grid = (unsigned)std::min<int64_t>(g.rows, 1 << 20);
+    if (op.mode == 0) pair_pack<<<grid, 256, 0, stream_>>>(g);
+    else pair_unpack<<<grid, 256, 0, stream_>>>(g);
+    launched(op.mode == 0 ? "pair pack" : "pair unpack");
     end();
   }
 

@@ -88,6 +88,42 @@ class HostBackend : public Backend {
     }
   }
 
+  void pairs(const PairOp& op) override {
+    const int64_t n1 = op.n1, n2 = op.n2;
+    const int64_t rest = op.pair2 ? n2 * n2 : n2;
+    const int64_t nq = op.pair2 ? n2 * (n2 - 1) / 2 : n2;
+    auto pidx = [](int64_t i, int64_t j, int64_t n) { return i * (2 * n - i - 1) / 2 + (j - i - 1); };
+    for (int64_t blk = 0; blk < op.nblk; ++blk)
+      for (int64_t i = 0; i < n1; ++i)
+        for (int64_t j = 0; j < n1; ++j)
+          for (int64_t c = 0; c < rest; ++c) {
+            const int64_t a = op.pair2 ? c / n2 : 0, b = op.pair2 ? c % n2 : c;
+            const int64_t xo = blk * op.x_bs + (i * n1 + j) * rest + c;
+            if (op.mode == 0) {
+              if (i >= j || (op.pair2 && a >= b)) continue;
+              const int64_t yo = blk * op.y_bs + pidx(i, j, n1) * nq + (op.pair2 ? pidx(a, b, n2) : b);
+              const int64_t xs = blk * op.x_bs + (j * n1 + i) * rest + c;
+              op.y_re[yo] = op.alpha * (op.x_re[xo] - (op.anti ? op.x_re[xs] : 0.0));
+              if (op.y_im) op.y_im[yo] = op.alpha * (op.x_im[xo] - (op.anti ? op.x_im[xs] : 0.0));
+            } else {
+              double vr = 0.0, vi = 0.0;
+              if (i != j && (!op.pair2 || a != b)) {
+                double sg = i < j ? 1.0 : -1.0;
+                int64_t q = b;
+                if (op.pair2) {
+                  q = pidx(std::min(a, b), std::max(a, b), n2);
+                  if (b < a) sg = -sg;
+                }
+                const int64_t yo = blk * op.y_bs + pidx(std::min(i, j), std::max(i, j), n1) * nq + q;
+                vr = op.alpha * sg * op.y_re[yo];
+                if (op.y_im) vi = op.alpha * sg * op.y_im[yo];
+              }
+              op.x_re[xo] = vr + (op.beta ? op.x_re[xo] : 0.0);
+              if (op.x_im) op.x_im[xo] = vi + (op.beta ? op.x_im[xo] : 0.0);
+            }
+          }
+  }
+
   void update(const UpdateOp& u) override {
     const int64_t n1 = u.lay.n1(), n2 = u.lay.n2(), no = u.lay.no, nv = u.lay.nv;
     const int64_t total = u.lay.size();

@@ -11,6 +11,7 @@ namespace {
 constexpr int64_t kComputeUnits = 256;   // MI355X
 constexpr int64_t kMinSplitK = 128;      // shortest K chunk worth a work-group
 constexpr int64_t kSmallK = 16;          // sums this short run on the vector units
+constexpr int64_t kBatchMaxK = 1024;     // longer sums: batch a product only over nearly full tiles
 constexpr int64_t kSplitMinK = 64;       // reduced precision: shortest sum whose operands are converted once
 constexpr double kSplitMinMacs = 1e9;    // ... and smallest product (MACs) worth the extra pass
 }  // namespace
@@ -168,6 +169,13 @@ void Engine::add(const View& out, const View& in, double alpha_re, double alpha_
   }
 }
 
+void Engine::pairs(const PairOp& op) {
+  if (dry) return;
+  be->set_phase(kPhaseMove);
+  be->pairs(op);
+  be->set_phase(phase);
+}
+
 void Engine::scale(const View& out, const double* const* scale_vecs) {
   add(out, out, 1.0, 0.0, 0, scale_vecs);
 }
@@ -233,8 +241,14 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
       std::string m2 = minus(Mg, c), n2 = minus(Ng, c), b2(1, c);
       if (flat(C, cl, b2, &s0) && flat(C, cl, m2, &s1) && flat(C, cl, n2, &s2)) {
         // promote only if the batched product fills its tiles nearly as well as
-        // one product into a temporary (which costs a permute of the output)
-        if (fill(m2, n2) < 0.6 * fill(Mg, Ng)) continue;
+        // one product into a temporary (which costs a permute of the output); a
+        // long sum makes the product compute bound, and there a batch of narrow
+        // products also re-reads its operands once per batch entry, so only
+        // (nearly) full tiles qualify
+        int64_t K = 1;
+        for (char k : Kg) K *= dim_of(k);
+        const double need = K >= kBatchMaxK ? 0.95 : 0.6;
+        if (fill(m2, n2) < need * fill(Mg, Ng)) continue;
         Bg = b2;
         Mg = m2;
         Ng = n2;

@@ -82,6 +82,8 @@ class Engine {
   // out = alpha * in + beta * out (same shape), optional per-dimension scale vectors
   void add(const View& out, const View& in, double alpha_re, double alpha_im, int beta,
            const double* const* scale = nullptr);
+  // pack / unpack antisymmetric pair storage (PairOp)
+  void pairs(const PairOp& op);
   // out *= prod_d scale_d (in place)
   void scale(const View& out, const double* const* scale);
   View temp(std::initializer_list<int64_t> dims, bool cplx);

@@ -68,6 +68,11 @@ struct Context {
   double* Jov = nullptr;               // (me|nf) as [m][e][n][f]
   double* Vlad = nullptr;              // (ae|bf) as [e][f][a][b]
   double* B1 = nullptr;                // (me|bf) as [e][f][m][b]
+  // Same-spin blocks in antisymmetric pair storage (pairs e < f, a < b in
+  // lexicographic order): <ab||ef> = (ae|bf) - (af|be) as [ef][ab], and
+  // (me|bf) - (mf|be) as [ef][m][b]
+  double* Wpp = nullptr;
+  double* B1p = nullptr;
   double *X = nullptr, *RHS = nullptr, *R = nullptr;   // amplitude sets
   double* delta = nullptr;
   double* epart = nullptr;
@@ -109,6 +114,16 @@ struct Context {
     return block(v, {r0, c0}, {nr, nc});
   }
   View vec(double* p, int64_t n) const { return make_view(p, nullptr, {n}); }
+  static int64_t npairs(int64_t n) { return n * (n - 1) / 2; }
+  // the two same-spin doubles blocks (0: alpha alpha, 2: beta beta) of a set and
+  // a packed [2][pairs (i<j)][...] array
+  PairOp same_spin_pairs(double* set_blocks, const View& packed, int64_t n2, int pair2) const {
+    PairOp op;
+    op.n1 = no; op.n2 = n2; op.nblk = 2; op.pair2 = pair2;
+    op.x_re = set_blocks; op.x_im = set_blocks + lay.size(); op.x_bs = 2 * lay.n2();
+    op.y_re = packed.re; op.y_im = packed.im; op.y_bs = packed.numel() / 2;
+    return op;
+  }
 
   double* take(int64_t n) { return arena.take(n); }
   void h2d(double* dst, const double* src, int64_t n) {
@@ -179,6 +194,8 @@ struct Context {
     Jov = take((int64_t)no * nv * no * nv);
     Vlad = take((int64_t)nv * nv * nv * nv);
     B1 = take((int64_t)nv * nv * no * nv);
+    Wpp = take(npairs(nv) * npairs(nv));
+    B1p = take(npairs(nv) * no * nv);
     const int64_t ns = lay.size();
     X = take(2 * ns);
     RHS = take(2 * ns);
@@ -299,6 +316,16 @@ struct Context {
         eng.contract("Qae,Qbf->efab", Le, Lv(Lvv, nv, nv), block(Vv, {e0, 0, 0, 0}, {n, nv, nv, nv}), 1.0, 0);
         eng.contract("Qme,Qbf->efmb", Lm, Lv(Lvv, nv, nv), block(Bv, {e0, 0, 0, 0}, {n, nv, no, nv}), 1.0, 0);
       }
+    }
+    {
+      PairOp w;
+      w.n1 = nv; w.n2 = nv; w.pair2 = 1; w.anti = 1;
+      w.x_re = Vlad; w.y_re = Wpp;
+      eng.pairs(w);
+      PairOp z;
+      z.n1 = nv; z.n2 = (int64_t)no * nv; z.pair2 = 0; z.anti = 1;
+      z.x_re = B1; z.y_re = B1p;
+      eng.pairs(z);
     }
     // T(0) = 0, C(0) = 0
     if (!dry) {
@@ -426,12 +453,29 @@ struct Context {
     const int64_t P3 = 3 * (int64_t)no * no;
     double* x2 = Xs + 2 * lay.n1();
     double* r2 = Rs + 2 * lay.n1();
-    View T3 = make_view(x2, x2 + lay.size(), {P3, nv, nv});
-    View R3 = make_view(r2, r2 + lay.size(), {P3, nv, nv});
-    // T1 part of the dressed virtual vectors ("Z" terms): Z_ij,mb = sum_ef T_ijef (me|bf)
+    // same-spin doubles in pair storage [2][i<j][e<f] (T is antisymmetric in both pairs)
+    const int64_t npo = npairs(no), npv = npairs(nv), nov = (int64_t)no * nv;
+    View Tp = eng.temp({2 * npo, npv}, true);
+    eng.pairs(same_spin_pairs(x2, Tp, nv, 1));
+    View Tab = make_view(x2 + lay.n2(), x2 + lay.size() + lay.n2(), {(int64_t)no * no, nv, nv});
+    View Rab = make_view(r2 + lay.n2(), r2 + lay.size() + lay.n2(), {(int64_t)no * no, nv, nv});
+    // T1 part of the dressed virtual vectors ("Z" terms): Z_ij,mb = sum_ef T_ijef (me|bf),
+    // for the same-spin blocks sum_{e<f} T_ijef [(me|bf) - (mf|be)] over pairs i < j
     View Z3 = eng.temp({P3, no, nv}, true);
     eng.set_phase(kPhaseRing);
-    eng.contract("Pef,efmb->Pmb", T3, Bv, Z3, 1.0, 0);
+    {
+      const int64_t zb = (int64_t)no * no * nov;
+      eng.contract("Pef,efmb->Pmb", Tab, Bv, make_view(Z3.re + zb, Z3.im + zb, {(int64_t)no * no, no, nv}), 1.0, 0);
+      const size_t mz = arena.mark();
+      View Zp = eng.temp({2 * npo, nov}, true);
+      eng.contract("Pq,qc->Pc", Tp, make_view(B1p, nullptr, {npv, nov}), Zp, 1.0, 0);
+      PairOp u;
+      u.n1 = no; u.n2 = nov; u.nblk = 2; u.pair2 = 0; u.mode = 1; u.beta = 0;
+      u.x_re = Z3.re; u.x_im = Z3.im; u.x_bs = 2 * zb;
+      u.y_re = Zp.re; u.y_im = Zp.im; u.y_bs = npo * nov;
+      eng.pairs(u);
+      arena.release(mz);
+    }
     eng.set_phase(kPhaseGemm);
     // same-spin doubles
     for (int s = 0; s < 2; ++s) {
@@ -505,9 +549,20 @@ struct Context {
       eng.contract("jmbe,maei->ijab", t2(Xs, 2), Vx[1], Rv, 1.0, 1);
       eng.set_phase(kPhaseGemm);
     }
-    // particle-particle ladder with the real (ae|bf), all three blocks in one GEMM
+    // particle-particle ladder with the real (ae|bf): the alpha-beta block in full
+    // storage, the same-spin blocks as sum_{e<f} T_ijef <ab||ef> over pairs i < j, a < b
     eng.set_phase(kPhaseLadder);
-    eng.contract("Pef,efab->Pab", T3, Vl, R3, 1.0, 1);
+    eng.contract("Pef,efab->Pab", Tab, Vl, Rab, 1.0, 1);
+    {
+      const size_t mz = arena.mark();
+      View Zp = eng.temp({2 * npo, npv}, true);
+      eng.contract("Pq,qr->Pr", Tp, make_view(Wpp, nullptr, {npv, npv}), Zp, 1.0, 0);
+      PairOp u = same_spin_pairs(r2, Zp, nv, 1);
+      u.mode = 1;
+      u.beta = 1;
+      eng.pairs(u);
+      arena.release(mz);
+    }
     eng.set_phase(kPhaseGemm);
     // zero the amplitudes of spin-orbitals that do not exist
     {

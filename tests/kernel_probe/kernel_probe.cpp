@@ -10,6 +10,7 @@
 #include <vector>
 #include <string>
 #include <chrono>
+#include <algorithm>
 #include "../../paper_2301_04249_amd/csrc/backend.h"
 using namespace rteom;
 
@@ -91,11 +92,12 @@ static int check(Backend* be) {
 static void bench(Backend* be) {
   struct S { long M, N, K; bool ac, bc, akc, bkc; const char* what; };
   S shapes[] = {
-    {3888, 26406, 105625, true, false, true, false, "ladder slab (Pef,efab->Pab), N quarter"},
+    {1296, 26406, 105625, true, false, true, false, "alpha-beta ladder (Pef,efab->Pab), N quarter"},
+    {1260, 52650, 52650, true, false, true, false, "same-spin ladder in pair storage"},
     {11700, 11700, 11700, true, true, true, false, "ring cc"},
     {11700, 11700, 11700, true, false, true, false, "ring cr"},
     {1296, 105625, 2000, false, false, false, false, "Qmj,Qbe real"},
-    {3888, 11700, 105625, true, false, true, false, "Z (Pef,efmb->Pmb)"},
+    {1296, 11700, 105625, true, false, true, false, "Z (Pef,efmb->Pmb), alpha-beta"},
     {192, 12321, 12321, true, false, true, false, "formaldehyde ladder"},
   };
   for (int prec = 0; prec < 3; ++prec)
@@ -188,11 +190,91 @@ static int check_permute(Backend* be) {
   return fails;
 }
 
+// Pair storage check: pack and unpack against host loops written from the
+// definition (lexicographic pairs, sign -1 per swapped pair), every flag combination.
+static int check_pairs(Backend* be) {
+  int fails = 0, runs = 0;
+  srand(11);
+  const int64_t dims[][2] = {{1, 5}, {2, 1}, {2, 3}, {5, 17}, {7, 40}, {36, 9}};
+  auto pidx = [](int64_t i, int64_t j, int64_t n) {   // position of (i < j) among the pairs of n
+    int64_t p = 0;
+    for (int64_t a = 0; a < i; ++a) p += n - 1 - a;
+    return p + (j - i - 1);
+  };
+  for (auto& d : dims)
+    for (int flags = 0; flags < 64; ++flags) {
+      const int64_t n1 = d[0], n2 = d[1];
+      const int pair2 = flags & 1, anti = (flags >> 1) & 1, mode = (flags >> 2) & 1, beta = (flags >> 3) & 1;
+      const bool cx = (flags >> 4) & 1;
+      const int64_t nblk = (flags >> 5) & 1 ? 2 : 1;
+      const int64_t rest = pair2 ? n2 * n2 : n2, np1 = n1 * (n1 - 1) / 2, nq = pair2 ? n2 * (n2 - 1) / 2 : n2;
+      const int64_t xbs = n1 * n1 * rest + 3, ybs = np1 * nq + 5;   // padded block strides
+      const int64_t nx = nblk * xbs, ny = nblk * ybs;
+      std::vector<double> x(2 * nx), y(2 * ny), xr, yr;
+      for (auto& v : x) v = rand() / (double)RAND_MAX - 0.5;
+      for (auto& v : y) v = rand() / (double)RAND_MAX - 0.5;
+      xr = x;
+      yr = y;
+      const double alpha = 0.625;
+      for (int64_t b = 0; b < nblk; ++b)
+        for (int64_t i = 0; i < n1; ++i)
+          for (int64_t j = 0; j < n1; ++j)
+            for (int64_t c = 0; c < rest; ++c) {
+              const int64_t a2 = pair2 ? c / n2 : 0, b2 = pair2 ? c % n2 : c;
+              const int64_t xo = b * xbs + (i * n1 + j) * rest + c;
+              for (int pl = 0; pl < (cx ? 2 : 1); ++pl) {
+                if (mode == 0) {
+                  if (i >= j || (pair2 && a2 >= b2)) continue;
+                  const int64_t yo = b * ybs + pidx(i, j, n1) * nq + (pair2 ? pidx(a2, b2, n2) : b2);
+                  const int64_t xs = b * xbs + (j * n1 + i) * rest + c;
+                  yr[pl * ny + yo] = alpha * (x[pl * nx + xo] - (anti ? x[pl * nx + xs] : 0.0));
+                } else {
+                  double v = beta ? x[pl * nx + xo] : 0.0;
+                  if (i != j && !(pair2 && a2 == b2)) {
+                    const int64_t q = pair2 ? pidx(std::min(a2, b2), std::max(a2, b2), n2) : b2;
+                    const double sg = (i < j ? 1.0 : -1.0) * (pair2 && b2 < a2 ? -1.0 : 1.0);
+                    v += alpha * sg * y[pl * ny + b * ybs + pidx(std::min(i, j), std::max(i, j), n1) * nq + q];
+                  }
+                  xr[pl * nx + xo] = v;
+                }
+              }
+            }
+      double* dx = (double*)be->alloc(16 * nx + 8);
+      double* dy = (double*)be->alloc(16 * ny + 8);
+      be->h2d(dx, x.data(), 16 * nx);
+      be->h2d(dy, y.data(), 16 * ny);
+      PairOp op;
+      op.n1 = n1; op.n2 = n2; op.nblk = nblk; op.pair2 = pair2; op.anti = anti; op.mode = mode; op.beta = beta;
+      op.alpha = alpha;
+      op.x_re = dx; op.x_im = cx ? dx + nx : nullptr; op.x_bs = xbs;
+      op.y_re = dy; op.y_im = cx ? dy + ny : nullptr; op.y_bs = ybs;
+      be->pairs(op);
+      be->sync();
+      std::vector<double> xo(2 * nx), yo(2 * ny);
+      be->d2h(xo.data(), dx, 16 * nx);
+      be->d2h(yo.data(), dy, 16 * ny);
+      double e = 0.0;
+      for (int64_t k = 0; k < 2 * nx; ++k) e = std::fmax(e, std::fabs(xo[k] - xr[k]));
+      for (int64_t k = 0; k < 2 * ny; ++k) e = std::fmax(e, std::fabs(yo[k] - yr[k]));
+      std::string m;
+      const bool ok = e <= 1e-15 && be->ok(&m);
+      ++runs;
+      if (!ok) {
+        ++fails;
+        printf("PAIRS FAIL n1 %ld n2 %ld flags %d err %.3g %s\n", (long)n1, (long)n2, flags, e, m.c_str());
+      }
+      be->release(dx);
+      be->release(dy);
+    }
+  printf("pairs probe: %d runs, %d failures\n", runs, fails);
+  return fails;
+}
+
 int main(int argc, char** argv) {
   std::string err;
   Backend* be = make_hip_backend(nullptr, &err);
   if (!be) { printf("no backend %s\n", err.c_str()); return 1; }
   if (argc > 1 && std::string(argv[1]) == "bench") { bench(be); return 0; }
-  const int f = check_permute(be);
+  const int f = check_permute(be) + check_pairs(be);
   return (check(be) || f) ? 2 : 0;
 }

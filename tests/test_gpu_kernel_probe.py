@@ -2,7 +2,7 @@
 every operand layout, complex combination, ragged size, split-K factor, broadcast batch and
 tile shape against host loops in float64 (1e-12), float32 (2e-5) and bf16x3 (2e-3); tile
 shapes and the converted-operand paths bitwise equal to the 64x64 result; permutes against
-host loops (1e-14)."""
+host loops (1e-14); pair storage pack/unpack against host loops written from the definition."""
 import os
 import subprocess
 
@@ -21,4 +21,6 @@ def test_kernel_probe():
     assert "permute probe:" in out.stdout and "gemm probe:" in out.stdout
     assert " 0 failures" in out.stdout.split("permute probe:")[1].splitlines()[0]
     assert " 0 failures" in out.stdout.split("gemm probe:")[1].splitlines()[0]
+    assert "pairs probe:" in out.stdout
+    assert " 0 failures" in out.stdout.split("pairs probe:")[1].splitlines()[0]
     assert out.returncode == 0

@@ -88,24 +88,28 @@ static int check(Backend* be) {
   return fails;
 }
 
-// Timing of each tile shape: (M, N, K, a complex, b complex, a k-contiguous, b k-contiguous)
+// Timing of each tile shape: (M, N, K, a complex, b complex, a k-contiguous, b
+// k-contiguous, largest split-K factor tried); operands hold only their real planes
+// when real.
 static void bench(Backend* be) {
-  struct S { long M, N, K; bool ac, bc, akc, bkc; const char* what; };
+  struct S { long M, N, K; bool ac, bc, akc, bkc; int max_split; const char* what; };
   S shapes[] = {
-    {1296, 26406, 105625, true, false, true, false, "alpha-beta ladder (Pef,efab->Pab), N quarter"},
-    {1260, 52650, 52650, true, false, true, false, "same-spin ladder in pair storage"},
-    {11700, 11700, 11700, true, true, true, false, "ring cc"},
-    {11700, 11700, 11700, true, false, true, false, "ring cr"},
-    {1296, 105625, 2000, false, false, false, false, "Qmj,Qbe real"},
-    {1296, 11700, 105625, true, false, true, false, "Z (Pef,efmb->Pmb), alpha-beta"},
-    {192, 12321, 12321, true, false, true, false, "formaldehyde ladder"},
+    {1296, 105625, 105625, true, false, true, false, 8, "alpha-beta ladder (Pef,efab->Pab)"},
+    {1260, 52650, 52650, true, false, true, false, 8, "same-spin ladder in pair storage"},
+    {11700, 11700, 11700, true, true, true, false, 1, "ring cc"},
+    {11700, 11700, 11700, true, false, true, false, 1, "ring cr"},
+    {1296, 105625, 2000, false, false, false, false, 1, "Qmj,Qbe real"},
+    {1296, 11700, 105625, true, false, true, false, 8, "Z (Pef,efmb->Pmb), alpha-beta"},
+    {192, 12321, 12321, true, false, true, false, 1, "formaldehyde ladder"},
   };
   for (int prec = 0; prec < 3; ++prec)
   for (auto& s : shapes) {
+    if (prec > 0 && s.max_split > 1 && s.N > 60000) continue;   // the float64 timing is the one needed
     long na = s.M * s.K, nb = s.K * s.N, nc = s.M * s.N;
-    double *dA = (double*)be->alloc(16 * na), *dB = (double*)be->alloc(16 * nb), *dC = (double*)be->alloc(16 * nc);
+    const long pa = s.ac ? 2 : 1, pb = s.bc ? 2 : 1, pc = (s.ac || s.bc) ? 2 : 1;
+    double *dA = (double*)be->alloc(8 * pa * na), *dB = (double*)be->alloc(8 * pb * nb), *dC = (double*)be->alloc(8 * pc * nc);
     if (!dA || !dB || !dC) { printf("alloc failed\n"); return; }
-    be->fill(dA, 2 * na, 0.001); be->fill(dB, 2 * nb, 0.002); be->fill(dC, 2 * nc, 0.0);
+    be->fill(dA, pa * na, 0.001); be->fill(dB, pb * nb, 0.002); be->fill(dC, pc * nc, 0.0);
     GemmOp g; g.M = s.M; g.N = s.N; g.K = s.K; g.batch = 1;
     g.a_sm = s.akc ? s.K : 1; g.a_sk = s.akc ? 1 : s.M; g.a_sb = 0;
     g.b_sk = s.bkc ? 1 : s.N; g.b_sn = s.bkc ? s.K : 1; g.b_sb = 0;
@@ -116,14 +120,19 @@ static void bench(Backend* be) {
     const double flops = 2.0 * mult * s.M * s.N * s.K;
     double* dS = nullptr;
     if (prec >= 1) { dS = (double*)be->alloc(8 * split_doubles(s.M, s.N, s.K, 1, 1, s.ac, s.bc, prec)); g.split = dS; }
+    double* dP = s.max_split > 1 ? (double*)be->alloc(8 * pc * s.max_split * nc) : nullptr;
+    for (int sk = 1; sk <= s.max_split; sk *= 2)
     for (int v = 0; v < (prec == 0 ? 6 : 4); ++v) {
+      if (sk > 1 && v != 1 && v != 4) continue;
+      g.splitk = sk;
+      g.partial = sk > 1 ? dP : nullptr;
       be->force_tile(v);
       be->gemm(g); be->sync();   // warm
       auto t0 = std::chrono::steady_clock::now();
       be->gemm(g); be->sync();
       double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      printf("prec=%d tile=%d %-40s M=%ld N=%ld K=%ld  %.3f ms  %.1f TFLOP/s\n", prec, v, s.what, s.M, s.N, s.K,
-             sec * 1e3, flops / sec / 1e12);
+      printf("prec=%d tile=%d split=%d %-36s M=%ld N=%ld K=%ld  %.3f ms  %.1f TFLOP/s\n", prec, v, sk, s.what, s.M, s.N,
+             s.K, sec * 1e3, flops / sec / 1e12);
       fflush(stdout);
     }
     be->force_tile(-1);
@@ -131,6 +140,7 @@ static void bench(Backend* be) {
     if (!be->ok(&m)) { printf("backend error %s\n", m.c_str()); return; }
     be->release(dA); be->release(dB); be->release(dC);
     if (dS) be->release(dS);
+    if (dP) be->release(dP);
   }
 }
 

@@ -242,9 +242,10 @@ __global__ __launch_bounds__(64 * GM * GN)
       // float64: the wave multiplying runs at raised priority, so that its MFMA
       // chain is not held up by the other wave on the SIMD staging its next tile
       if constexpr (sizeof(T) == 8) __builtin_amdgcn_s_setprio(1);
-      // Wide per-wave tiles and 8-wave work-groups keep fragments of one (float64)
-      // or two (float32) k-steps in flight instead of four (register budget).
-#pragma unroll ((WM * WN <= 4 && GM * GN == 4) ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
+      // Four-wave work-groups unroll the whole K tile; eight-wave ones (at most 128
+      // registers per wave) keep fragments of one (float64) or two (float32) k-steps
+      // in flight.
+#pragma unroll (GM * GN == 4 ? BK / 4 : (sizeof(T) == 8 ? 1 : 2))
       for (int ks = 0; ks < BK / 4; ++ks) {
         const int kr = ks * 4 + (lane >> 4);
         T a_r[WM], a_i[WM], b_r[WN], b_i[WN];

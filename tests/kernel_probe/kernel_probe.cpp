@@ -91,18 +91,18 @@ static int check(Backend* be) {
 // Timing of each tile shape: (M, N, K, a complex, b complex, a k-contiguous, b
 // k-contiguous, largest split-K factor tried); operands hold only their real planes
 // when real.
-static void bench(Backend* be) {
+static void bench(Backend* be, int max_prec) {
   struct S { long M, N, K; bool ac, bc, akc, bkc; int max_split; const char* what; };
   S shapes[] = {
-    {1296, 105625, 105625, true, false, true, false, 8, "alpha-beta ladder (Pef,efab->Pab)"},
-    {1260, 52650, 52650, true, false, true, false, 8, "same-spin ladder in pair storage"},
+    {1296, 105625, 105625, true, false, true, false, 1, "alpha-beta ladder (Pef,efab->Pab)"},
+    {1260, 52650, 52650, true, false, true, false, 1, "same-spin ladder in pair storage"},
     {11700, 11700, 11700, true, true, true, false, 1, "ring cc"},
     {11700, 11700, 11700, true, false, true, false, 1, "ring cr"},
     {1296, 105625, 2000, false, false, false, false, 1, "Qmj,Qbe real"},
-    {1296, 11700, 105625, true, false, true, false, 8, "Z (Pef,efmb->Pmb), alpha-beta"},
+    {1296, 11700, 105625, true, false, true, false, 1, "Z (Pef,efmb->Pmb), alpha-beta"},
     {192, 12321, 12321, true, false, true, false, 1, "formaldehyde ladder"},
   };
-  for (int prec = 0; prec < 3; ++prec)
+  for (int prec = 0; prec <= max_prec; ++prec)
   for (auto& s : shapes) {
     if (prec > 0 && s.max_split > 1 && s.N > 60000) continue;   // the float64 timing is the one needed
     long na = s.M * s.K, nb = s.K * s.N, nc = s.M * s.N;
@@ -284,7 +284,7 @@ int main(int argc, char** argv) {
   std::string err;
   Backend* be = make_hip_backend(nullptr, &err);
   if (!be) { printf("no backend %s\n", err.c_str()); return 1; }
-  if (argc > 1 && std::string(argv[1]) == "bench") { bench(be); return 0; }
+  if (argc > 1 && std::string(argv[1]) == "bench") { bench(be, argc > 2 ? atoi(argv[2]) : 2); return 0; }
   const int f = check_permute(be) + check_pairs(be);
   return (check(be) || f) ? 2 : 0;
 }

@@ -588,9 +588,24 @@ __global__ __launch_bounds__(256) void f32_kernel(const double* src, int64_t row
   }
 }
 
+typedef float f16v __attribute__((ext_vector_type(16)));
+
+__device__ inline f16v mma3_32(bf8 ah, bf8 al, bf8 bh, bf8 bl, f16v c) {
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
+  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+  return c;
+}
+
+// bf16x3 product of pre-split operands on the 32 x 32 x 16 bf16 matrix cores:
+// twice the products of the 16 x 16 x 32 form per fragment read from LDS, which
+// bounds these short bf16 k-steps.  Work-group tile (64 WM) x (64 WN), 2 x 2 waves
+// of WM x WN blocks of 32 x 32; a fragment lane holds row (lane % 32) and k
+// (lane / 32) * 8 .. + 7 of its block; accumulator register r of a lane holds row
+// 8 (r / 4) + 4 (lane / 32) + r % 4 and column lane % 32.
 template <bool AC, bool BC, int WM, int WN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_bf16x3_split(GemmArgs g) {
-  constexpr int TM = 32 * WM, TN = 32 * WN, LDK = BKH + PADH;
+  constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BKH + PADH;
   constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
   constexpr int CA = TM / 64, CB = TN / 64;             // 16-byte chunks per thread and plane
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
@@ -613,13 +628,16 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
   }
   for (int64_t b = b0; b < g.batch; b += bstep) {
     const int64_t ao = b * g.sab, bo = b * g.sbb;
-    f4 accr[WM][WN], acci[WM][WN];
+    f16v accr[WM][WN], acci[WM][WN];
 #pragma unroll
     for (int x = 0; x < WM; ++x)
 #pragma unroll
       for (int y = 0; y < WN; ++y) {
-        accr[x][y] = f4{0.f, 0.f, 0.f, 0.f};
-        acci[x][y] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accr[x][y][r] = 0.f;
+          acci[x][y][r] = 0.f;
+        }
       }
     u4 ra[PA][CA], rb[PB][CB];
     auto fetch = [&](int64_t k0) {
@@ -654,40 +672,44 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
     }
     __syncthreads();
     int buf = 0;
-    const int kk = (lane >> 4) * 8;
+    const int l32 = lane & 31, kh = (lane >> 5) * 8;
     for (int64_t k0 = kbeg; k0 < kend; k0 += BKH) {
       const bool more = k0 + BKH < kend;
       if (more) fetch(k0 + BKH);
-      bf8 xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
 #pragma unroll
-      for (int x = 0; x < WM; ++x) {
-        const int row = wm * 16 * WM + x * 16 + (lane & 15);
-        xrh[x] = ld8(&sa[buf][0][row][kk]);
-        xrl[x] = ld8(&sa[buf][1][row][kk]);
-        if (AC) { xih[x] = ld8(&sa[buf][2 % PA][row][kk]); xil[x] = ld8(&sa[buf][3 % PA][row][kk]); }
-      }
+      for (int ks = 0; ks < BKH / 16; ++ks) {
+        const int kk = ks * 16 + kh;
+        bf8 xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
 #pragma unroll
-      for (int y = 0; y < WN; ++y) {
-        const int col = wn * 16 * WN + y * 16 + (lane & 15);
-        yrh[y] = ld8(&sb[buf][0][col][kk]);
-        yrl[y] = ld8(&sb[buf][1][col][kk]);
-        if (BC) { yih[y] = ld8(&sb[buf][2 % PB][col][kk]); yil[y] = ld8(&sb[buf][3 % PB][col][kk]); }
-      }
-#pragma unroll
-      for (int x = 0; x < WM; ++x)
+        for (int x = 0; x < WM; ++x) {
+          const int row = wm * 32 * WM + x * 32 + l32;
+          xrh[x] = ld8(&sa[buf][0][row][kk]);
+          xrl[x] = ld8(&sa[buf][1][row][kk]);
+          if (AC) { xih[x] = ld8(&sa[buf][2 % PA][row][kk]); xil[x] = ld8(&sa[buf][3 % PA][row][kk]); }
+        }
 #pragma unroll
         for (int y = 0; y < WN; ++y) {
-          accr[x][y] = mma3(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
-          if (AC && BC) {
-            accr[x][y] = mma3(neg8(xih[x]), neg8(xil[x]), yih[y], yil[y], accr[x][y]);
-            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
-            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
-          } else if (AC) {
-            acci[x][y] = mma3(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
-          } else if (BC) {
-            acci[x][y] = mma3(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
-          }
+          const int col = wn * 32 * WN + y * 32 + l32;
+          yrh[y] = ld8(&sb[buf][0][col][kk]);
+          yrl[y] = ld8(&sb[buf][1][col][kk]);
+          if (BC) { yih[y] = ld8(&sb[buf][2 % PB][col][kk]); yil[y] = ld8(&sb[buf][3 % PB][col][kk]); }
         }
+#pragma unroll
+        for (int x = 0; x < WM; ++x)
+#pragma unroll
+          for (int y = 0; y < WN; ++y) {
+            accr[x][y] = mma3_32(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
+            if (AC && BC) {
+              accr[x][y] = mma3_32(neg8(xih[x]), neg8(xil[x]), yih[y], yil[y], accr[x][y]);
+              acci[x][y] = mma3_32(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+              acci[x][y] = mma3_32(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+            } else if (AC) {
+              acci[x][y] = mma3_32(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+            } else if (BC) {
+              acci[x][y] = mma3_32(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+            }
+          }
+      }
       if (more) stage(buf ^ 1);
       __syncthreads();
       buf ^= 1;
@@ -701,9 +723,9 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
 #pragma unroll
       for (int y = 0; y < WN; ++y)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t gm = m0 + wm * 16 * WM + x * 16 + 4 * (lane >> 4) + r;
-          const int64_t gn = n0 + wn * 16 * WN + y * 16 + (lane & 15);
+        for (int r = 0; r < 16; ++r) {
+          const int64_t gm = m0 + wm * 32 * WM + x * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int64_t gn = n0 + wn * 32 * WN + y * 32 + l32;
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * sm + gn * sn;
             if (split) {
@@ -1321,10 +1343,10 @@ bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
 
 template <bool AC, bool BC>
 bool launch_split(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if (v == 0) return launch_split_tile<AC, BC, 2, 2, 0>(grid, st, g);
-  if (v == 1) return launch_split_tile<AC, BC, 2, 4, 1>(grid, st, g);
-  if (v == 2) return launch_split_tile<AC, BC, 4, 2, 2>(grid, st, g);
-  if (v == 3) return launch_split_tile<AC, BC, 4, 4, 3>(grid, st, g);
+  if (v == 0) return launch_split_tile<AC, BC, 1, 1, 0>(grid, st, g);
+  if (v == 1) return launch_split_tile<AC, BC, 1, 2, 1>(grid, st, g);
+  if (v == 2) return launch_split_tile<AC, BC, 2, 1, 2>(grid, st, g);
+  if (v == 3) return launch_split_tile<AC, BC, 2, 2, 3>(grid, st, g);
   return false;
 }
 

@@ -36,6 +36,12 @@ struct GemmOp {
   // operand's batch stride is 0): bf16 hi/lo planes
   // for bf16x3, float planes for fp32.  nullptr = convert while staging.
   double* split = nullptr;
+  // A real B held converted outside the scratch (a constant operand): its planes
+  // ([N][ld], the layout the conversion above gives B) are at b_conv; with
+  // b_conv_fill = 1 this product converts B into them first, else it reads them
+  // as they are.  The scratch then holds A's planes only.
+  double* b_conv = nullptr;
+  int b_conv_fill = 0;
 };
 
 // K granularity of converted planes, and the scratch (in doubles) they need.
@@ -49,6 +55,10 @@ inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch_a, i
   // bf16x3: two 2-byte planes per real plane; fp32: one 4-byte plane; +64 for alignment
   return (prec == 2 ? (2 * el + 3) / 4 : (el + 1) / 2) + 64;
 }
+
+// Doubles that hold one real operand of `rows` rows converted for a sum of K: two
+// bf16 planes or one float plane, [rows][split_ld(K)] each (+64 for alignment).
+inline int64_t conv_doubles(int64_t rows, int64_t K) { return (rows * split_ld(K) + 1) / 2 + 64; }
 
 // out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an
 // nd-dimensional index space; strides per operand.  in may be real while out is

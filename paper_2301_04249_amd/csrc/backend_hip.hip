@@ -1546,9 +1546,10 @@ class HipBackend : public Backend {
     const int64_t asz = nba * op.M * ld, bsz = nbb * op.N * ld;
     unsigned short* base = reinterpret_cast<unsigned short*>(op.split);
     const int pa = ac ? 4 : 2, pb = bc ? 4 : 2;
+    unsigned short* bbase = op.b_conv ? reinterpret_cast<unsigned short*>(op.b_conv) : base + pa * asz;
     for (int p = 0; p < 4; ++p) {
       g.sa[p] = p < pa ? base + p * asz : nullptr;
-      g.sb[p] = p < pb ? base + pa * asz + p * bsz : nullptr;
+      g.sb[p] = p < pb ? bbase + p * bsz : nullptr;
     }
     g.sld = ld;
     g.sab = op.a_sb ? op.M * ld : 0;
@@ -1562,6 +1563,7 @@ class HipBackend : public Backend {
     };
     run(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, g.sa[0], g.sa[1]);
     if (ac) run(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, g.sa[2], g.sa[3]);
+    if (op.b_conv && !op.b_conv_fill) return;   // B converted by an earlier product
     run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[0], g.sb[1]);
     if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, g.sb[2], g.sb[3]);
   }
@@ -1573,6 +1575,7 @@ class HipBackend : public Backend {
     const int64_t asz = nba * op.M * ld, bsz = nbb * op.N * ld;
     float* base = reinterpret_cast<float*>(op.split);
     float* pl[4] = {base, ac ? base + asz : nullptr, base + (ac ? 2 : 1) * asz, nullptr};
+    if (op.b_conv) pl[2] = reinterpret_cast<float*>(op.b_conv);
     pl[3] = bc ? pl[2] + bsz : nullptr;
     auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, float* d) {
       dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
@@ -1581,8 +1584,10 @@ class HipBackend : public Backend {
     };
     run(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, pl[0]);
     if (ac) run(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, pl[1]);
-    run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, pl[2]);
-    if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, pl[3]);
+    if (!op.b_conv || op.b_conv_fill) {
+      run(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, pl[2]);
+      if (bc) run(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, pl[3]);
+    }
     g.ar = reinterpret_cast<const double*>(pl[0]);
     g.ai = reinterpret_cast<const double*>(pl[1]);
     g.br = reinterpret_cast<const double*>(pl[2]);

@@ -181,7 +181,7 @@ void Engine::scale(const View& out, const double* const* scale_vecs) {
 }
 
 void Engine::contract(const char* spec_str, const View& A, const View& B, const View& C,
-                      double alpha, int beta) {
+                      double alpha, int beta, ConvSlot* b_slot) {
   Spec sp = parse(spec_str);
   if ((int)sp.a.size() != A.nd || (int)sp.b.size() != B.nd || (int)sp.c.size() != C.nd)
     throw Error(1, std::string("contract: rank does not match spec ") + spec_str);
@@ -375,9 +375,27 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   // Reduced precisions: large products convert their operands once (bf16 hi/lo
   // planes, or float planes) instead of in every work-group that stages them
   if (prec != 0 && op.K >= kSplitMinK && static_cast<double>(op.M) * op.N * op.K * op.batch >= kSplitMinMacs &&
-      op.M >= 64 && op.N >= 64)
-    op.split = scratch->take(split_doubles(op.M, op.N, op.K, op.a_sb ? op.batch : 1, op.b_sb ? op.batch : 1,
-                                           op.a_im != nullptr, op.b_im != nullptr, prec));
+      op.M >= 64 && op.N >= 64) {
+    // a constant B (the caller's slot), used as it is (no copy) and alone in its batch
+    const bool resident = b_slot && b_slot->p && op.b_im == nullptr && op.batch == 1 && Bu.re == B.re &&
+                          conv_doubles(op.N, op.K) <= b_slot->doubles;
+    if (resident) {
+      if (b_slot->ready && (b_slot->rows != op.N || b_slot->k != op.K || b_slot->s_row != op.b_sn ||
+                            b_slot->s_k != op.b_sk))
+        throw Error(1, std::string("contract: converted operand layout changed in ") + spec_str);
+      op.b_conv = b_slot->p;
+      op.b_conv_fill = b_slot->ready ? 0 : 1;
+      if (!dry) {
+        b_slot->ready = true;
+        b_slot->rows = op.N;
+        b_slot->k = op.K;
+        b_slot->s_row = op.b_sn;
+        b_slot->s_k = op.b_sk;
+      }
+    }
+    op.split = scratch->take(split_doubles(op.M, resident ? 0 : op.N, op.K, op.a_sb ? op.batch : 1,
+                                           op.b_sb ? op.batch : 1, op.a_im != nullptr, op.b_im != nullptr, prec));
+  }
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
 #ifdef RTEOM_PLAN_TRACE

@@ -59,6 +59,16 @@ class Arena {
   bool counting_ = false;
 };
 
+// Resident converted copy of a constant real B operand (reduced precisions): the
+// first product that uses it converts B into it, later products with the same B
+// layout read it as it is.
+struct ConvSlot {
+  double* p = nullptr;
+  int64_t doubles = 0;
+  bool ready = false;
+  int64_t rows = 0, k = 0, s_row = 0, s_k = 0;   // layout it holds once ready
+};
+
 class Engine {
  public:
   Backend* be = nullptr;
@@ -78,7 +88,7 @@ class Engine {
   // A&C: rows, B&C: columns, A&B: summed.  Operands whose index groups cannot be
   // flattened to single strides are copied to a temporary first.
   void contract(const char* spec, const View& A, const View& B, const View& C, double alpha,
-                int beta);
+                int beta, ConvSlot* b_slot = nullptr);
   // out = alpha * in + beta * out (same shape), optional per-dimension scale vectors
   void add(const View& out, const View& in, double alpha_re, double alpha_im, int beta,
            const double* const* scale = nullptr);

@@ -28,6 +28,7 @@
 #include <memory>
 #include <new>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/rteom.h"
@@ -73,6 +74,9 @@ struct Context {
   // (me|bf) - (mf|be) as [ef][m][b]
   double* Wpp = nullptr;
   double* B1p = nullptr;
+  // reduced precisions: the contractions' converted copies of those constant blocks
+  // (ladder, same-spin ladder, alpha-beta Z, same-spin Z), made by their first use
+  ConvSlot conv_v, conv_w, conv_b1, conv_b1p;
   double *X = nullptr, *RHS = nullptr, *R = nullptr;   // amplitude sets
   double* delta = nullptr;
   double* epart = nullptr;
@@ -196,6 +200,17 @@ struct Context {
     B1 = take((int64_t)nv * nv * no * nv);
     Wpp = take(npairs(nv) * npairs(nv));
     B1p = take(npairs(nv) * no * nv);
+    if (opt.prec != RTEOM_FP64) {
+      const int64_t v2 = (int64_t)nv * nv, pv = npairs(nv), ov = (int64_t)no * nv;
+      const std::pair<ConvSlot*, int64_t> slots[4] = {
+          {&conv_v, conv_doubles(v2, v2)}, {&conv_w, conv_doubles(pv, pv)},
+          {&conv_b1, conv_doubles(ov, v2)}, {&conv_b1p, conv_doubles(ov, pv)}};
+      for (const auto& sl : slots) {
+        *sl.first = ConvSlot();
+        sl.first->doubles = sl.second;
+        sl.first->p = take(sl.second);
+      }
+    }
     const int64_t ns = lay.size();
     X = take(2 * ns);
     RHS = take(2 * ns);
@@ -465,10 +480,11 @@ struct Context {
     eng.set_phase(kPhaseRing);
     {
       const int64_t zb = (int64_t)no * no * nov;
-      eng.contract("Pef,efmb->Pmb", Tab, Bv, make_view(Z3.re + zb, Z3.im + zb, {(int64_t)no * no, no, nv}), 1.0, 0);
+      eng.contract("Pef,efmb->Pmb", Tab, Bv, make_view(Z3.re + zb, Z3.im + zb, {(int64_t)no * no, no, nv}), 1.0, 0,
+                   &conv_b1);
       const size_t mz = arena.mark();
       View Zp = eng.temp({2 * npo, nov}, true);
-      eng.contract("Pq,qc->Pc", Tp, make_view(B1p, nullptr, {npv, nov}), Zp, 1.0, 0);
+      eng.contract("Pq,qc->Pc", Tp, make_view(B1p, nullptr, {npv, nov}), Zp, 1.0, 0, &conv_b1p);
       PairOp u;
       u.n1 = no; u.n2 = nov; u.nblk = 2; u.pair2 = 0; u.mode = 1; u.beta = 0;
       u.x_re = Z3.re; u.x_im = Z3.im; u.x_bs = 2 * zb;
@@ -552,11 +568,11 @@ struct Context {
     // particle-particle ladder with the real (ae|bf): the alpha-beta block in full
     // storage, the same-spin blocks as sum_{e<f} T_ijef <ab||ef> over pairs i < j, a < b
     eng.set_phase(kPhaseLadder);
-    eng.contract("Pef,efab->Pab", Tab, Vl, Rab, 1.0, 1);
+    eng.contract("Pef,efab->Pab", Tab, Vl, Rab, 1.0, 1, &conv_v);
     {
       const size_t mz = arena.mark();
       View Zp = eng.temp({2 * npo, npv}, true);
-      eng.contract("Pq,qr->Pr", Tp, make_view(Wpp, nullptr, {npv, npv}), Zp, 1.0, 0);
+      eng.contract("Pq,qr->Pr", Tp, make_view(Wpp, nullptr, {npv, npv}), Zp, 1.0, 0, &conv_w);
       PairOp u = same_spin_pairs(r2, Zp, nv, 1);
       u.mode = 1;
       u.beta = 1;

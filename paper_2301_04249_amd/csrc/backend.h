@@ -198,6 +198,7 @@ class Backend {
   // Stream capture of a fixed sequence of operations into a replayable graph
   // (returns false where not supported: the caller then issues operations directly).
   virtual bool begin_capture() { return false; }
+  virtual bool capturing() const { return false; }
   virtual void* end_capture() { return nullptr; }
   virtual void launch_graph(void* exec) { (void)exec; }
   virtual void destroy_graph(void* exec) { (void)exec; }

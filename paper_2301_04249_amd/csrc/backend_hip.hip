@@ -1817,6 +1817,7 @@ class HipBackend : public Backend {
     record(hipStreamBeginCapture(stream_, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
     return err_.empty();
   }
+  bool capturing() const override { return capturing_; }
   void* end_capture() override {
     hipGraph_t graph = nullptr;
     record(hipStreamEndCapture(stream_, &graph), "hipStreamEndCapture");

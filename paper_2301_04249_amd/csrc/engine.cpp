@@ -383,6 +383,10 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
       if (b_slot->ready && (b_slot->rows != op.N || b_slot->k != op.K || b_slot->s_row != op.b_sn ||
                             b_slot->s_k != op.b_sk))
         throw Error(1, std::string("contract: converted operand layout changed in ") + spec_str);
+      // the conversion is written once, outside graph capture (a discarded capture
+      // would leave the slot marked but never written)
+      if (!b_slot->ready && !dry && be->capturing())
+        throw Error(1, std::string("contract: converted operand first used inside a graph capture in ") + spec_str);
       op.b_conv = b_slot->p;
       op.b_conv_fill = b_slot->ready ? 0 : 1;
       if (!dry) {

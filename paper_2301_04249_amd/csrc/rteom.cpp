@@ -1033,7 +1033,9 @@ rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t
     c.init(fock_diag, chol);
     // Graph-captured steps cannot time GEMM tile shapes: tune them now on one
     // residual evaluation (at T = 0; only shapes matter), outside any capture.
-    if (o.tune && c.graph_mode()) {
+    // The same residual writes the resident converted integral blocks of the
+    // reduced precisions, so that no captured graph holds their conversion.
+    if ((o.tune || o.prec != RTEOM_FP64) && c.graph_mode()) {
       c.residual(c.X, c.R);
       c.be->sync();
     }

@@ -98,7 +98,11 @@ typedef struct {
    dC_include_fT1 = 1, no graph, max_steps = 100000, null stream, no workspace, tune = 1. */
 void rteom_default_options(rteom_options* opt);
 
-/* Device bytes rteom_init needs for these sizes and options (no GPU work). */
+/* Device bytes rteom_init needs for these sizes and options (no GPU work): the resident
+   integral blocks, three amplitude sets (plus the Anderson history), the scratch of one
+   residual evaluation and, with FP32 or BF16X3 contractions, the converted planes of the
+   constant integral blocks (e.g. 176.5 GiB for FP64 and 241 GiB reduced at o = 36,
+   v = 324, Q = 2000). */
 rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
                                    int32_t n_chol, int32_t core_orb, int32_t core_spin,
                                    const rteom_options* opt, size_t* bytes);
@@ -179,7 +183,9 @@ rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_
                         int32_t* vir_list);
 
 /* Replace the current amplitudes (host layout above).  Entries of non-existent spin
-   amplitudes are ignored (set to zero).  Test and benchmark hook. */
+   amplitudes are ignored (set to zero).  The same-spin doubles must be antisymmetric
+   in (i,j) and (a,b): the particle-particle ladder and the (me|bf) terms of those
+   blocks read the pairs i<j, a<b only.  Test and benchmark hook. */
 rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double* t2);
 
 /* Copy the current amplitudes to host (layout above). */
@@ -194,7 +200,8 @@ rteom_status rteom_residual(rteom_ctx* ctx, double* r1_out, double* r2_out);
 rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
 
 /* Floating-point operations of one residual evaluation as this implementation performs
-   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex).
+   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex; the
+   same-spin ladder and (me|bf) terms over their unique pairs).
    Known from rteom_init on (the contraction plan fixes it). */
 rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
 

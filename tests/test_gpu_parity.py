@@ -28,6 +28,8 @@ def _prop(eps, chol, na, nb, co, cs, **kw):
     (4, 16, 48, 4, 4, 0, 1, 1.0),       # tiny workload shape
     (4, 16, 48, 4, 4, 2, 0, 1.0),
     (6, 29, 70, 6, 6, 0, 1, 1.0),       # several 64-wide tiles with ragged tails
+    (1, 3, 10, 1, 1, 0, 1, 3.0),        # no same-spin occupied pair (pair storage empty)
+    (2, 2, 10, 2, 2, 1, 1, 3.0),        # one occupied and one virtual pair per spin
 ])
 def test_residual_parity(case):
     o, v, q, na, nb, co, cs, sc = case

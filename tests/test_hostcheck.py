@@ -22,6 +22,8 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="host-check libr
 
 @pytest.mark.parametrize("case", [
     (3, 4, 3, 3, 0, 1), (3, 4, 3, 3, 0, 0), (3, 4, 3, 2, 1, 0), (4, 5, 4, 4, 1, 1), (2, 3, 2, 1, 0, 0),
+    # same-spin pair storage with no pair (one occupied orbital) and with a single pair
+    (1, 3, 1, 1, 0, 1), (2, 1, 2, 2, 0, 1), (2, 2, 2, 2, 1, 1),
 ])
 def test_residual_and_energy_vs_oracle(case):
     o, v, na, nb, co, cs = case

@@ -199,9 +199,10 @@ rteom_status rteom_residual(rteom_ctx* ctx, double* r1_out, double* r2_out);
 /* <Phi|(H_N e^T)_C|Phi> at the current amplitudes (Eq. cum_gf3), e_out = (re, im). */
 rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
 
-/* Floating-point operations of one residual evaluation as this implementation performs
-   them (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex; the
-   same-spin ladder and (me|bf) terms over their unique pairs).
+/* Floating-point operations of one residual evaluation in this implementation's
+   formulation (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex
+   even where the kernels form a complex product from three real ones; the same-spin
+   ladder and (me|bf) terms over their unique pairs).
    Known from rteom_init on (the contraction plan fixes it). */
 rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
 

@@ -182,13 +182,18 @@ __global__ __launch_bounds__(64 * GM * GN)
   const int a_thr = (int)((am0 * g.asm_ + ak0 * g.ask) * (int64_t)sizeof(S));
   const int b_thr = (int)((bn0 * g.bsn + bk0 * g.bsk) * (int64_t)sizeof(S));
   for (int64_t b = b0; b < g.batch; b += bstep) {
-    acc_t accr[WM][WN], acci[WM][WN];
+    // complex x complex in three real products (Gauss): accr = sum Ar Br,
+    // acci = sum Ai Bi, accs = sum (Ar + Ai)(Br + Bi); re = accr - acci,
+    // im = accs - accr - acci.  Otherwise accr, acci are the real and imaginary sums.
+    constexpr bool G3 = AC && BC;
+    acc_t accr[WM][WN], acci[WM][WN], accs[G3 ? WM : 1][G3 ? WN : 1];
 #pragma unroll
     for (int x = 0; x < WM; ++x)
 #pragma unroll
       for (int y = 0; y < WN; ++y) {
         accr[x][y] = acc_t{0, 0, 0, 0};
         acci[x][y] = acc_t{0, 0, 0, 0};
+        if constexpr (G3) accs[x][y] = acc_t{0, 0, 0, 0};
       }
     S pa_r[NA], pa_i[NA], pb_r[NB], pb_i[NB];
     const int64_t a_org = b * g.asb + m0 * g.asm_, b_org = b * g.bsb + n0 * g.bsn;
@@ -264,15 +269,21 @@ __global__ __launch_bounds__(64 * GM * GN)
           b_r[y] = (&sb_r[buf][0][0])[ib];
           b_i[y] = BC ? (&sb_i[buf][0][0])[ib] : (T)0;
         }
+        T a_s[G3 ? WM : 1], b_s[G3 ? WN : 1];
+        if constexpr (G3) {
+#pragma unroll
+          for (int x = 0; x < WM; ++x) a_s[x] = a_r[x] + a_i[x];
+#pragma unroll
+          for (int y = 0; y < WN; ++y) b_s[y] = b_r[y] + b_i[y];
+        }
 #pragma unroll
         for (int x = 0; x < WM; ++x)
 #pragma unroll
           for (int y = 0; y < WN; ++y) {
             accr[x][y] = Mfma<T>::mma(a_r[x], b_r[y], accr[x][y]);
-            if (AC && BC) {
-              accr[x][y] = Mfma<T>::mma(-a_i[x], b_i[y], accr[x][y]);
-              acci[x][y] = Mfma<T>::mma(a_r[x], b_i[y], acci[x][y]);
-              acci[x][y] = Mfma<T>::mma(a_i[x], b_r[y], acci[x][y]);
+            if constexpr (G3) {
+              acci[x][y] = Mfma<T>::mma(a_i[x], b_i[y], acci[x][y]);
+              accs[x][y] = Mfma<T>::mma(a_s[x], b_s[y], accs[x][y]);
             } else if (AC) {
               acci[x][y] = Mfma<T>::mma(a_i[x], b_r[y], acci[x][y]);
             } else if (BC) {
@@ -300,15 +311,21 @@ __global__ __launch_bounds__(64 * GM * GN)
           const int64_t gn = n0 + wn * 16 * WN + y * 16 + (lane & 15);
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * sm + gn * sn;
+            double pr = (double)accr[x][y][r], pi = (double)acci[x][y][r];
+            if constexpr (G3) {
+              const double p1 = pr, p2 = pi;
+              pr = p1 - p2;
+              pi = (double)accs[x][y][r] - p1 - p2;
+            }
             if (split) {
-              Cr[o] = (double)accr[x][y][r];
-              if (AC || BC) Ci[o] = (double)acci[x][y][r];
+              Cr[o] = pr;
+              if (AC || BC) Ci[o] = pi;
             } else {
-              double vr = g.alpha * (double)accr[x][y][r];
+              double vr = g.alpha * pr;
               if (g.beta) vr += Cr[o];
               Cr[o] = vr;
               if (AC || BC) {
-                double vi = g.alpha * (double)acci[x][y][r];
+                double vi = g.alpha * pi;
                 if (g.beta) vi += Ci[o];
                 Ci[o] = vi;
               }

@@ -219,7 +219,7 @@ def main(argv=None):
         print(json.dumps({"copy_probe_bytes": n * 8}))
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build measures one GPU only (single-GPU hot path); run with --gpus 1",
+        print("bench.py: the benchmark runs on one GPU (the hot path of one propagation per GPU); run with --gpus 1",
               file=sys.stderr)
         return 2
 

@@ -186,6 +186,20 @@ def test_graph_replay_matches_direct_launches():
     assert np.array_equal(a.get_amplitudes()[1], b.get_amplitudes()[1])
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_graph_replay_reduced_precision(prec):
+    """Reduced precisions keep converted planes of the constant integral blocks; a graph-mode
+    context writes them at init, before any capture, so its replayed steps equal direct
+    launches bitwise (formaldehyde shape: the alpha-beta ladder takes the converted path)."""
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1)
+    a = _prop(eps, chol, 8, 8, 0, 1, prec=prec, fixed_iters=2, tune=False)
+    b = _prop(eps, chol, 8, 8, 0, 1, prec=prec, fixed_iters=2, tune=False, graph=True)
+    a.step(0.025, 4)
+    b.step(0.025, 4)
+    assert np.all(np.isfinite(a.cumulant()[1]))
+    assert np.array_equal(a.cumulant()[1], b.cumulant()[1])
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_tile_shape_choice_is_bit_identical(prec):
     """GEMM tile shapes differ only in how output tiles are assigned to work-groups: the

@@ -49,6 +49,7 @@ struct GemmArgs {
   int64_t kchunk;             // K elements per split (multiple of BK)
   double* pr; double* pi;     // partials [splitk][M][N]
   int m_fast;                 // logical tile order: row tiles fastest (B is the larger operand)
+  int prio;                   // float64: raise the wave priority around the MFMA block
   // pre-split bf16 planes (gemm_bf16x3_split): A planes [batch][M][sld], B planes
   // [batch][N][sld] in the order re hi, re lo, im hi, im lo
   const unsigned short* sa[4];
@@ -244,12 +245,10 @@ __global__ __launch_bounds__(64 * GM * GN)
     for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
       const bool more = k0 + BK < kend;
       if (more) fetch(k0 + BK);
-      // float64 complex x complex and eight-wave tiles: the wave multiplying runs at
-      // raised priority, so that its MFMA chain is not held up by another wave on the
-      // SIMD staging its next tile (four-wave complex x real and real tiles run 3-6 %
-      // faster without it, measured over whole time steps)
-      constexpr bool kPrio = sizeof(T) == 8 && (GM * GN == 8 || (AC && BC));
-      if constexpr (kPrio) __builtin_amdgcn_s_setprio(1);
+      // float64 (g.prio): the wave multiplying runs at raised priority, so that its
+      // MFMA chain is not held up by another wave on the SIMD staging its next tile
+      constexpr bool kPrio = sizeof(T) == 8;
+      if (kPrio && g.prio) __builtin_amdgcn_s_setprio(1);
       // Four-wave work-groups unroll the whole K tile; eight-wave ones (at most 128
       // registers per wave) keep fragments of one (float64) or two (float32) k-steps
       // in flight.
@@ -291,7 +290,7 @@ __global__ __launch_bounds__(64 * GM * GN)
             }
           }
       }
-      if constexpr (kPrio) __builtin_amdgcn_s_setprio(0);
+      if (kPrio && g.prio) __builtin_amdgcn_s_setprio(0);
       if (more) stage(buf ^ 1);
       __syncthreads();
       buf ^= 1;
@@ -1528,6 +1527,12 @@ class HipBackend : public Backend {
       g.pr = op.partial;
       g.pi = cplx ? op.partial + (int64_t)g.splitk * op.M * op.N : nullptr;
     }
+    // Wave priority: raised while a work-group's sum is shorter than 65536 k; longer
+    // ones (the particle-particle ladder) keep the default, which lets the work-groups
+    // sharing an operand panel stay closer in k, so that the XCD L2 serves more of it
+    // (whole-step A/B: the long ladder 3.6 % faster without, the shorter products 1-3 %
+    // faster with)
+    g.prio = g.kchunk < 65536 ? 1 : 0;
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
     const bool presplit = op.prec != 0 && op.split != nullptr;

@@ -32,6 +32,9 @@ KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands 
 # summaries (with the commands) are under profiles/.  Only workloads whose
 # ladder kernel has been counted since its last change are listed.
 TRAFFIC = {
+    # profiles/gemm_mfma_ladder_esca_fp64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, mean of the
+    # alpha-beta and same-spin ladder launches
+    ("esca", "fp64"): 7.94e11,
 }
 
 DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",

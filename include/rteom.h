@@ -77,7 +77,9 @@ typedef struct {
   double fp_tol;           /* max |T^(k+1) - T^(k)| over all amplitudes that ends the passes */
   int32_t dC_include_fT1;  /* 1: dC/dt includes sum f_ia t_ia (Eq. cum_gf3); 0: Eq. dcdt as printed */
   int32_t graph;           /* 1: with fp_fixed_iters > 0 and a non-null stream, each time step
-                              is captured once as a hipGraph and replayed */
+                              is captured once as a hipGraph and replayed; rteom_init then
+                              runs one residual outside capture (GEMM tile timing with
+                              tune = 1, and the converted integral planes of FP32 / BF16X3) */
   int64_t max_steps;       /* capacity of the device C(t) history (time steps) */
   void* stream;            /* hipStream_t borrowed from the caller; NULL = null stream */
   void* workspace;         /* caller-owned device memory, or NULL (library allocates) */

@@ -287,6 +287,48 @@ def test_green_function_and_spectrum_free_particle():
     assert np.abs(a - lorentz).max() < 2e-2 * lorentz.max()
 
 
+def test_spectrum_of_linear_cumulant_closed_form():
+    """Eqs. cum_gf, cum_gf2 with a nonzero cumulant C(tau) = (-a + i b) tau and a nonzero
+    E_N^corr: every damped trapezoid term is a power z^n of one complex number, so the
+    discrete transform is a geometric sum, and A = -(1/pi) Im of it in closed form.  The
+    peak sits at eps_c + E_N^corr - b with half-width a + eta: the sign of C in exp(C), the
+    sign of the E_N^corr phase and the trapezoid end weights all change A here."""
+    dt, n = 0.05, 2400
+    times = np.arange(n + 1) * dt
+    a_c, b_c, eps_c, e_corr, eta = 0.04, 0.3, -20.0, -0.11, 0.02
+    cum = (-a_c + 1j * b_c) * times
+    g = propagate.green_function(times, cum, eps_c, e_corr)
+    omegas = np.linspace(-21.0, -19.0, 801)
+    a = propagate.spectral_function(times, g, omegas, eta)
+    z = np.exp((1j * (omegas - eps_c - e_corr + b_c) - (a_c + eta)) * dt)
+    geo = (1 - z ** (n + 1)) / (1 - z) - 0.5 * (1 + z ** n)
+    closed = -(-1j * dt * geo).imag / np.pi
+    assert np.abs(a - closed).max() < 1e-11 * closed.max()
+    # continuum limit: a Lorentzian of half-width a + eta at eps_c + E_N^corr - b
+    w0, gam = eps_c + e_corr - b_c, a_c + eta
+    lorentz = gam / np.pi / ((omegas - w0) ** 2 + gam ** 2)
+    assert np.abs(a - lorentz).max() < 2e-3 * lorentz.max()
+    assert abs(propagate.qp_peak(omegas, a) - w0) < 2e-4
+
+
+def test_qp_peak_refinement_between_grid_points():
+    """The QP position is refined by the parabola through the grid maximum and its two
+    neighbours: exact for samples of a parabola whose vertex lies between grid points, and
+    for a Lorentzian far closer to its centre than the grid spacing."""
+    omegas = np.linspace(-20.5, -19.5, 1001)        # spacing 1e-3
+    h = omegas[1] - omegas[0]
+    for w0 in (-20.0 + 0.37 * h, -19.9 - 0.21 * h, -20.3 + 0.49 * h):
+        y = 5.0 - 3.0 * (omegas - w0) ** 2
+        assert abs(propagate.qp_peak(omegas, y) - w0) < 1e-9 * h
+        k = int(np.argmax(y))
+        assert abs(omegas[k] - w0) > 0.2 * h           # the refinement moved the estimate
+    gam, w0 = 0.01, -20.0 + 0.43 * h
+    lor = gam / ((omegas - w0) ** 2 + gam ** 2)
+    assert abs(propagate.qp_peak(omegas, lor) - w0) < 5e-3 * h     # raw arg-max: 0.43 h off
+    # a peak on the first or last grid point is returned as it is
+    assert propagate.qp_peak(omegas, -(omegas + 20.5) ** 2) == omegas[0]
+
+
 def test_lean_mode_matches_dense():
     """Lean blocks and the per-spin Coulomb particle ladder equal the dense <pq||rs> path."""
     eps, chol = draw_system(Shape(3, 6, 14), cfg=5, chol_scale=2.0)

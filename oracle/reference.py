@@ -153,19 +153,32 @@ def particle_ladder(sys: SpinOrbitalSystem, tau: np.ndarray) -> np.ndarray:
         return 0.5 * np.einsum("ijef,abef->ijab", tau, sys.block("vvvv"), optimize=True)
     n = sys.n
     vir = sys.vir
-    spat = np.unique(vir % n)
-    pos = {int(p): k for k, p in enumerate(spat)}
-    lv = sys.chol[:, spat][:, :, spat]
-    vsp = np.einsum("kae,kbf->aebf", lv, lv, optimize=True)   # spatial (ae|bf)
+    if "ladder" not in sys._cache:
+        # constant per system: for each spin pair (sa, sb) the spatial (ae|bf) with a, e
+        # of spin sa and b, f of spin sb, as the real matrix [(e, f)][(a, b)]
+        spat = np.unique(vir % n)
+        pos = {int(p): k for k, p in enumerate(spat)}
+        lv = sys.chol[:, spat][:, :, spat]
+        vsp = np.einsum("kae,kbf->aebf", lv, lv, optimize=True)   # spatial (ae|bf)
+        mats = {}
+        for sa in (0, 1):
+            A = np.nonzero(vir // n == sa)[0]
+            ia = [pos[int(vir[k] % n)] for k in A]
+            for sb in (0, 1):
+                B = np.nonzero(vir // n == sb)[0]
+                ib = [pos[int(vir[k] % n)] for k in B]
+                v = vsp[np.ix_(ia, ia, ib, ib)]          # [a, e, b, f]
+                mats[sa, sb] = (A, B, np.ascontiguousarray(v.transpose(1, 3, 0, 2)).reshape(
+                    len(A) * len(B), len(A) * len(B)))
+        del vsp
+        sys._cache["ladder"] = mats
+    no2 = tau.shape[0] * tau.shape[1]
     out = np.zeros(tau.shape[:2] + (len(vir), len(vir)), dtype=complex)
-    for sa in (0, 1):
-        A = np.nonzero(vir // n == sa)[0]
-        ia = [pos[int(vir[k] % n)] for k in A]
-        for sb in (0, 1):
-            B = np.nonzero(vir // n == sb)[0]
-            ib = [pos[int(vir[k] % n)] for k in B]
-            v = vsp[np.ix_(ia, ia, ib, ib)]          # (a e | b f), a,e in spin sa; b,f in spin sb
-            out[np.ix_(np.arange(tau.shape[0]), np.arange(tau.shape[1]), A, B)] = np.einsum(
-                "ijef,aebf->ijab", tau[np.ix_(np.arange(tau.shape[0]), np.arange(tau.shape[1]), A, B)], v,
-                optimize=True)
+    for (A, B, m) in sys._cache["ladder"].values():
+        # out_ijab = sum_ef tau_ijef (ae|bf) for this spin pair: a real matrix product on the
+        # real and the imaginary part of tau
+        t = np.ascontiguousarray(tau[:, :, A][:, :, :, B]).reshape(no2, len(A) * len(B))
+        prod = (np.ascontiguousarray(t.real) @ m) + 1j * (np.ascontiguousarray(t.imag) @ m)
+        out[np.ix_(np.arange(tau.shape[0]), np.arange(tau.shape[1]), A, B)] = prod.reshape(
+            tau.shape[0], tau.shape[1], len(A), len(B))
     return out

@@ -57,8 +57,8 @@ typedef enum {
   RTEOM_ERR_ARG = 1,        /* invalid argument (sizes, indices, dt, options) */
   RTEOM_ERR_OOM = 2,        /* workspace too small or device allocation failed */
   RTEOM_ERR_HIP = 3,        /* a HIP runtime call failed */
-  RTEOM_ERR_NOCONV = 4,     /* fixed point not converged; the step is not committed */
-  RTEOM_ERR_NONFINITE = 5,  /* NaN/Inf in the inputs or in the amplitudes */
+  RTEOM_ERR_NOCONV = 4,     /* fixed point not converged; the step is not committed (T, C(t) unchanged) */
+  RTEOM_ERR_NONFINITE = 5,  /* NaN/Inf in the inputs, or in the amplitudes or C(t) during a step */
   RTEOM_ERR_STATE = 6       /* call not valid in the context's current state */
 } rteom_status;
 
@@ -123,15 +123,24 @@ rteom_status rteom_init(rteom_ctx** ctx, int32_t n_orb, int32_t n_occ_a, int32_t
                         int32_t core_orb, int32_t core_spin, const rteom_options* opt);
 
 /* Advance n_steps time steps of length dt (Eq. trapzrule with fixed-point passes) and
-   append C(t) for each.  micro_iters_out (nullable, host [n_steps]) receives the passes
-   used per step.  NOCONV (or NONFINITE) leaves C(t) at the last committed step, the
-   amplitudes at the last iterate, and the context in a failed state (STATE) until
-   amplitudes are set or a checkpoint is restored. */
+   append C(t) for each (Eq. cum_gf3).  micro_iters_out (nullable, host [n_steps])
+   receives the passes used per step.  Synchronises the stream.
+   Tolerance-driven steps (fp_fixed_iters = 0) keep T_n (one more amplitude set of
+   workspace): a step whose fixed point does not converge within fp_max_iter passes
+   (NOCONV) or whose iterate turns NaN/Inf (NONFINITE) is not committed -- T and C(t)
+   stay at the last committed step and the context remains usable (e.g. with a smaller
+   dt).  Fixed-pass and graph-replayed steps check once per call, after the stream has
+   drained, a device flag that the C(t) append raises when E(T) or C(t) is not finite
+   (E sums every amplitude times an integral, so one NaN/Inf amplitude makes it so):
+   then NONFINITE, C(t) holds the appended steps, and the context is in a failed state
+   (STATE) until amplitudes are set or a checkpoint is restored. */
 rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* micro_iters_out);
 
-/* Copy the cumulant history to host: t_out [cap] times, c_out [cap][2] (re, im) of
-   C(t_0 = 0) ... C(t_n); *n_out = number written (steps taken + 1, at most cap).
-   cap = 0 is a length query: nothing is written and *n_out = steps taken + 1. */
+/* Copy the cumulant history to host (Eq. cum_gf3: C(tau) = i int_0^tau
+   <Phi|(H_N e^T)_C|Phi> dtau', accumulated with the trapezoid weights of the time grid,
+   C(0) = 0): t_out [cap] times, c_out [cap][2] (re, im) of C(t_0 = 0) ... C(t_n);
+   *n_out = number written (steps taken + 1, at most cap).  cap = 0 is a length query:
+   nothing is written and *n_out = steps taken + 1.  Synchronises the stream. */
 rteom_status rteom_cumulant(const rteom_ctx* ctx, int64_t cap, double* t_out, double* c_out,
                             int64_t* n_out);
 
@@ -224,7 +233,9 @@ rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double
    simultaneously").  Every context must be in graph mode with fixed passes, on its own
    stream; the batch borrows them (they must outlive it).  rteom_batch_step advances all of
    them by n_steps of dt with one graph launch per step: a graph whose independent child
-   nodes are the contexts' captured time steps.  Synchronises on return. */
+   nodes are the contexts' captured time steps.  Synchronises on return; then checks every
+   member's non-finite flag (as rteom_step does) and returns NONFINITE naming the first
+   member whose E(T) or C(t) turned NaN/Inf (that member enters its failed state). */
 rteom_status rteom_batch_create(rteom_batch** batch, int32_t n, rteom_ctx* const* ctxs);
 rteom_status rteom_batch_step(rteom_batch* batch, double dt, int32_t n_steps);
 rteom_status rteom_batch_free(rteom_batch* batch);   /* NULL-safe; leaves the contexts */

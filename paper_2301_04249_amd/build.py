@@ -1,7 +1,8 @@
 """Build the in-tree libraries.
 
 librteom.so            the product: C ABI + engine + gfx950 HIP kernels.
-librteom_hostcheck.so  test build of the same engine over host loops (tests/_hostcheck/),
+librteom_hostcheck.so  test build of the same engine over host loops (tests/hostcheck/backend_host.cpp,
+                       output in tests/_hostcheck/),
                        used only by CPU tests of the host logic; never loaded by the package.
 kernel_probe           test program (tests/kernel_probe/) that checks the GEMM and permute
                        kernels of librteom.so against host loops; run by a GPU test.
@@ -56,8 +57,10 @@ def build_hostcheck():
     outdir = os.path.join(ROOT, "tests", "_hostcheck")
     os.makedirs(outdir, exist_ok=True)
     out = os.path.join(outdir, "librteom_hostcheck.so")
-    srcs = [os.path.join(CSRC, s) for s in ("engine.cpp", "rteom.cpp", "backend_host.cpp")]
-    _run(["g++", "-O2", "-g", "-std=c++17", "-fPIC", "-shared", "-DRTEOM_HOST_BACKEND", *srcs, "-o", out + ".tmp"])
+    srcs = [os.path.join(CSRC, s) for s in ("engine.cpp", "rteom.cpp")]
+    srcs.append(os.path.join(ROOT, "tests", "hostcheck", "backend_host.cpp"))
+    _run(["g++", "-O2", "-g", "-std=c++17", "-fPIC", "-shared", "-DRTEOM_HOST_BACKEND", f"-I{CSRC}", *srcs,
+          "-o", out + ".tmp"])
     os.replace(out + ".tmp", out)
     return out
 

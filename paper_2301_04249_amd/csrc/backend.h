@@ -184,8 +184,11 @@ class Backend {
   virtual void energy(const EnergyOp& op) = 0;
   // With k = *step (device): C[k+1] = C[k] + i h (E[k] + e_next), E[k+1] = e_next,
   // *step = k + 1.  c_hist, e_hist: device (re, im) pairs; e_next: device pair.
+  // *bad (device) becomes 1 if e_next or C[k+1] is not finite and is never cleared
+  // here: E(T) sums every amplitude times an integral, so it is NaN or infinite as
+  // soon as one amplitude is.
   virtual void cumulant_append(double* c_hist, double* e_hist, const double* e_next,
-                               int64_t* step, double h) = 0;
+                               int64_t* step, double h, double* bad) = 0;
   // *out = sum_k a[k] b[k] (device pointers), summed in a fixed order; part is
   // scratch of energy_partials() doubles.
   virtual void dot(const double* a, const double* b, int64_t n, double* part, double* out) = 0;

@@ -1168,15 +1168,17 @@ __global__ __launch_bounds__(64) void dot_pass2(const double* part, int nparts, 
   if (threadIdx.x == 0) out[0] = acc;
 }
 
-__global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t* step, double h) {
+__global__ void cumulant_kernel(double* c, double* e, const double* en, int64_t* step, double h, double* bad) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     const int64_t k = *step;
     const double sr = e[2 * k] + en[0], si = e[2 * k + 1] + en[1];
-    c[2 * (k + 1)] = c[2 * k] - h * si;
-    c[2 * (k + 1) + 1] = c[2 * k + 1] + h * sr;
+    const double cr = c[2 * k] - h * si, ci = c[2 * k + 1] + h * sr;
+    c[2 * (k + 1)] = cr;
+    c[2 * (k + 1) + 1] = ci;
     e[2 * (k + 1)] = en[0];
     e[2 * (k + 1) + 1] = en[1];
     *step = k + 1;
+    if (!isfinite(en[0]) || !isfinite(en[1]) || !isfinite(cr) || !isfinite(ci)) *bad = 1.0;
   }
 }
 
@@ -1808,9 +1810,9 @@ class HipBackend : public Backend {
     end();
   }
 
-  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h) override {
+  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h, double* bad) override {
     begin();
-    cumulant_kernel<<<1, 64, 0, stream_>>>(c, e, en, step, h);
+    cumulant_kernel<<<1, 64, 0, stream_>>>(c, e, en, step, h, bad);
     launched("cumulant");
     end();
   }

@@ -78,7 +78,10 @@ struct Context {
   // (ladder, same-spin ladder, alpha-beta Z, same-spin Z), made by their first use
   ConvSlot conv_v, conv_w, conv_b1, conv_b1p;
   double *X = nullptr, *RHS = nullptr, *R = nullptr;   // amplitude sets
+  double* Tn = nullptr;      // T_n kept by tolerance-driven steps (restored if a step fails)
+  bool restored = false;     // the last failed step left T and C(t) as they were
   double* delta = nullptr;
+  double* dbad = nullptr;    // device flag: a non-finite E(T) or C(t) was appended
   double* epart = nullptr;
   double* e_hist = nullptr;  // [(max_steps+1)][2]
   double* e_next = nullptr;  // E(T_{n+1}) of the step in flight
@@ -215,7 +218,9 @@ struct Context {
     X = take(2 * ns);
     RHS = take(2 * ns);
     R = take(2 * ns);
+    if (opt.fp_fixed_iters == 0) Tn = take(2 * ns);
     delta = take(1);
+    dbad = take(1);
     epart = take(be ? be->energy_partials() : 4096);
     e_hist = take(2 * (opt.max_steps + 1));
     c_hist = take(2 * (opt.max_steps + 1));
@@ -348,6 +353,7 @@ struct Context {
       be->fill(e_hist, 2, 0.0);
       be->fill(c_hist, 2, 0.0);
       be->fill(reinterpret_cast<double*>(dstep), 1, 0.0);   // all-zero bits: integer 0
+      be->fill(dbad, 1, 0.0);
     }
     nsteps = 0;
     times.assign(1, 0.0);
@@ -642,6 +648,16 @@ struct Context {
     return passes;
   }
 
+  // After the stream has drained: did any step of the call append a non-finite E or C?
+  void check_finite() {
+    if (dry) return;
+    double b = 0.0;
+    be->d2h(&b, dbad, sizeof(double));
+    if (b != 0.0)
+      throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitudes: E(T) or C(t) of step " + std::to_string(nsteps) +
+                                           " or earlier is NaN or infinite");
+  }
+
   // Fixed-pass steps may be captured once into a graph and replayed: every
   // argument of a step is either constant or read from device memory.
   bool graph_mode() const { return opt.graph != 0 && opt.fp_fixed_iters > 0; }
@@ -795,10 +811,20 @@ struct Context {
     throw Error(RTEOM_ERR_NOCONV, "ground-state CCSD not converged in " + std::to_string(max_iter) + " iterations");
   }
 
+  // A tolerance-driven step that fails puts T_n back: the step is not committed.
+  [[noreturn]] void fail_step(int code, const std::string& m) {
+    be->d2d(X, Tn, sizeof(double) * 2 * lay.size());
+    be->sync();
+    restored = true;
+    throw Error(code, m);
+  }
+
   int enqueue_step(double dt) {
     UpdateOp u0 = update_op(true);
     u0.h = 0.5 * dt;
     const bool accel = am > 0 && opt.fp_fixed_iters == 0;   // tolerance-driven passes only
+    restored = false;
+    if (opt.fp_fixed_iters == 0) be->d2d(Tn, X, sizeof(double) * 2 * lay.size());
     if (accel) anderson_reset();
     residual(X, R);
     if (accel) anderson_keep_x();
@@ -820,10 +846,10 @@ struct Context {
       double d = 0.0;
       be->d2h(&d, delta, sizeof(double));
       while (!(d < opt.fp_tol)) {
-        if (!std::isfinite(d)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitudes in the fixed point");
+        if (!std::isfinite(d)) fail_step(RTEOM_ERR_NONFINITE, "non-finite amplitudes in the fixed point");
         if (passes >= opt.fp_max_iter)
-          throw Error(RTEOM_ERR_NOCONV, "fixed point not converged after " + std::to_string(passes) +
-                                            " passes (last change " + std::to_string(d) + ")");
+          fail_step(RTEOM_ERR_NOCONV, "fixed point not converged after " + std::to_string(passes) +
+                                          " passes (last change " + std::to_string(d) + ")");
         if (accel) anderson_mix();
         residual(X, R);
         if (accel) anderson_keep_x();
@@ -836,7 +862,7 @@ struct Context {
     }
     be->set_phase(kPhaseEnergy);
     energy(X, e_next);
-    be->cumulant_append(c_hist, e_hist, e_next, dstep, 0.5 * dt);
+    be->cumulant_append(c_hist, e_hist, e_next, dstep, 0.5 * dt, dbad);
     return passes;
   }
 };
@@ -1062,8 +1088,11 @@ rteom_status rteom_step(rteom_ctx* ctx, double dt, int32_t n_steps, int32_t* ite
       if (iters) iters[k] = p;
     }
     c.be->sync();
+    c.check_finite();
   });
-  if (st == RTEOM_ERR_NOCONV || st == RTEOM_ERR_NONFINITE || st == RTEOM_ERR_HIP) c.failed = true;
+  // a tolerance-driven step that failed left T and C(t) at the last committed step;
+  // anything else that fails leaves the context unusable until it is reset
+  if (st == RTEOM_ERR_HIP || ((st == RTEOM_ERR_NOCONV || st == RTEOM_ERR_NONFINITE) && !c.restored)) c.failed = true;
   return st;
 }
 
@@ -1153,6 +1182,7 @@ rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len) {
     c.be->h2d(c.X, d + 5 * n, sizeof(double) * amp);
     const int64_t step = h.nsteps;
     c.be->h2d(c.dstep, &step, sizeof(step));
+    c.be->fill(c.dbad, 1, 0.0);
     c.nsteps = h.nsteps;
     c.times.assign(d, d + n);
     c.failed = false;
@@ -1256,6 +1286,7 @@ rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double
       c.eng.scale(c.t2(c.X, b), sc);
     }
     c.energy(c.X, c.e_hist + 2 * c.nsteps);   // E(T_n) for the next trapezoid
+    c.be->fill(c.dbad, 1, 0.0);
     c.failed = false;
   });
 }
@@ -1377,6 +1408,16 @@ rteom_status rteom_batch_step(rteom_batch* b, double dt, int32_t n_steps) {
       }
     }
     lead->c.be->sync();
+    for (size_t k = 0; k < b->ctxs.size(); ++k) {
+      Context& x = b->ctxs[k]->c;
+      try {
+        x.check_finite();
+      } catch (const Error& e) {
+        x.failed = true;
+        x.err = e.what();
+        throw Error(e.code, "batch member " + std::to_string(k) + ": " + e.what());
+      }
+    }
   });
   if (st != RTEOM_OK) g_last_error = lead->c.err;
   return st;

@@ -267,7 +267,7 @@ class HostBackend : public Backend {
     qp[1] = a[best];
   }
 
-  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h) override {
+  void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h, double* bad) override {
     // C + i h (E_k + E_{k+1})
     const int64_t k = *step;
     const double sr = e[2 * k] + en[0], si = e[2 * k + 1] + en[1];
@@ -276,6 +276,9 @@ class HostBackend : public Backend {
     e[2 * (k + 1)] = en[0];
     e[2 * (k + 1) + 1] = en[1];
     *step = k + 1;
+    if (!std::isfinite(en[0]) || !std::isfinite(en[1]) || !std::isfinite(c[2 * (k + 1)]) ||
+        !std::isfinite(c[2 * (k + 1) + 1]))
+      *bad = 1.0;
   }
 };
 

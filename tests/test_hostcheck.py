@@ -55,15 +55,44 @@ def test_propagation_vs_oracle(kw):
     assert np.allclose(t, tr.times)
 
 
-def test_noconvergence_reported():
+def test_noconvergence_leaves_the_state_unchanged():
+    """NOCONV: the step is not committed -- T and C(t) stay at the last committed step and
+    the context stays usable (the next step with another dt continues from there)."""
     eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
-    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, tol=1e-14, max_iter=2)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, tol=1e-12, max_iter=20)
+    P.step(0.01, 2)                    # 11 passes per step
+    t_before, c_before = P.cumulant()
+    amp_before = P.get_amplitudes()
     with pytest.raises(rteom.RteomError) as ex:
-        P.step(0.05, 1)
+        P.step(0.05, 1)                # too long for 20 passes to reach 1e-12
     assert ex.value.status == 4
+    t_after, c_after = P.cumulant()
+    assert np.array_equal(t_after, t_before) and np.array_equal(c_after, c_before)
+    assert all(np.array_equal(x, y) for x, y in zip(P.get_amplitudes(), amp_before))
+    P.step(0.01, 1)                    # usable: continues from the committed step
+    sysm = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    tr = propagate.propagate(sysm, 0.01, 3, tol=1e-12, max_iter=20)
+    assert np.abs(P.cumulant()[1] - tr.cumulant).max() < 1e-14
+
+
+def test_nonfinite_fixed_pass_steps_are_reported():
+    """Fixed-pass steps have no convergence test; a dt far beyond the stable range makes the
+    amplitudes overflow, and rteom_step reports NONFINITE (from the device flag the C(t)
+    append raises) and puts the context in its failed state until a checkpoint is restored."""
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0, chol_scale=3.0)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, fixed_iters=3)
+    P.step(0.01, 2)
+    img = P.checkpoint()
     with pytest.raises(rteom.RteomError) as ex:
-        P.step(0.05, 1)
-    assert ex.value.status == 6   # failed state until amplitudes are reset
+        P.step(40.0, 30)
+    assert ex.value.status == 5
+    with pytest.raises(rteom.RteomError) as ex:
+        P.step(0.01, 1)
+    assert ex.value.status == 6
+    P.restore(img)
+    P.step(0.01, 1)                    # usable again, and finite
+    t, c = P.cumulant()
+    assert len(c) == 4 and np.all(np.isfinite(c))
 
 
 def test_input_validation():
@@ -125,7 +154,7 @@ def test_spectral_function_vs_oracle():
 def test_checkpoint_restart_continues_bitwise():
     """A propagation checkpointed after 6 steps and restored into a fresh context continues
     exactly as the uninterrupted one; foreign or truncated images are rejected, and a
-    restore clears the failed state left by a non-converged step."""
+    restore clears the failed state left by fixed-pass steps that overflowed."""
     eps, chol = draw_system(Shape(3, 5, 12), cfg=6, chol_scale=2.0)
     a = rteom.Propagator(eps, chol, 3, 3, 0, 1, fixed_iters=3, lib_path=LIB)
     a.step(0.05, 6)
@@ -146,9 +175,10 @@ def test_checkpoint_restart_continues_bitwise():
         assert ex.value.status == 1
     with pytest.raises(rteom.RteomError):
         other.restore(img)
-    c = rteom.Propagator(eps, chol, 3, 3, 0, 1, tol=1e-14, max_iter=2, lib_path=LIB)
-    with pytest.raises(rteom.RteomError):
-        c.step(0.05, 1)
+    c = rteom.Propagator(eps, chol, 3, 3, 0, 1, fixed_iters=3, lib_path=LIB)
+    with pytest.raises(rteom.RteomError) as ex:
+        c.step(40.0, 30)
+    assert ex.value.status == 5          # NaN/Inf amplitudes
     with pytest.raises(rteom.RteomError) as ex:
         c.checkpoint()
     assert ex.value.status == 6          # failed state

@@ -33,11 +33,15 @@
  *   amplitudes with i = core) are identically zero.
  * - Host amplitude layout (rteom_set_amplitudes / get / residual): complex
  *   numbers as interleaved (re, im) doubles;
- *     t1: [2 spins][n_o][n_v]                     (alpha, beta)
- *     t2: [3 blocks][n_o][n_o][n_v][n_v]          (aa, ab, bb)
- *   t1[s][i][a] = t_{i s}^{a s};  t2[aa][i][j][a][b] = t_{i a, j a}^{a a, b a}
- *   (antisymmetric in i,j and in a,b), t2[ab][i][j][a][b] =
- *   t_{i alpha, j beta}^{a alpha, b beta}, t2[bb] like aa for beta.
+ *     t1: [2 spins][n_o][n_v]                              (alpha, beta)
+ *     t2: [2 spins][P_o][P_v], then [n_o][n_o][n_v][n_v]   (aa, bb pairs; ab)
+ *   with P_o = n_o (n_o - 1) / 2, P_v = n_v (n_v - 1) / 2.
+ *   t1[s][i][a] = t_{i s}^{a s}.  The same-spin doubles t_{i s, j s}^{a s, b s}
+ *   are antisymmetric in (i, j) and in (a, b): only i < j, a < b are stored, at
+ *   pair positions p(i, j) = i (2 n_o - i - 1) / 2 + j - i - 1 and likewise
+ *   p(a, b) over n_v (lexicographic pairs).  The alpha-beta block holds
+ *   t_{i alpha, j beta}^{a alpha, b beta} at [i][j][a][b].  The device sets use
+ *   the same order, planar (all real parts, then all imaginary parts).
  */
 #ifndef RTEOM_H
 #define RTEOM_H
@@ -68,6 +72,15 @@ typedef enum {
   RTEOM_BF16X3 = 2  /* bf16 hi/lo split, three MFMA products, float32 accumulation */
 } rteom_prec;
 
+/* Memory plan.  Every intermediate that grows like o^2 v^2 or faster is produced in
+   blocks when the whole would not fit: the ring intermediates W[(m,e),(b,j)] in blocks
+   of occupied columns j, expanded same-spin amplitudes in blocks of rows, and -- when
+   they cannot stay resident -- the integral blocks (ae|bf), (me|bf) and their
+   same-spin pair forms, rebuilt from the Cholesky vectors in slabs of virtual indices
+   for every residual evaluation (Sec. 2.3).  rteom_init picks the largest blocks whose
+   workspace fits rteom_options.mem_limit (and the caller's workspace); every element is
+   computed by the same arithmetic under any plan. */
+
 typedef struct {
   uint32_t struct_size;    /* must be sizeof(rteom_options) */
   int32_t prec;            /* rteom_prec of the contractions; update and C(t) stay float64 */
@@ -94,17 +107,23 @@ typedef struct {
                               G(x_j) with the weights (sum 1) that minimise the norm of
                               the mixed G(x_j) - x_j; 0 = plain iteration.  Costs 2 m
                               amplitude sets of workspace. */
+  size_t mem_limit;        /* bytes the memory plan may use (0 = 270 GiB: MI355X HBM less
+                              room for the runtime); a caller's workspace lowers it */
+  int32_t plan_slab;       /* 0: automatic plan; > 0: the integral blocks are rebuilt per
+                              residual in slabs of this many virtual indices */
+  int32_t plan_block;      /* 0: automatic; > 0: occupied indices per block of the ring
+                              intermediates and of the expanded same-spin rows.  With either
+                              set, the plan is used as given (OOM if it does not fit). */
 } rteom_options;
 
 /* Fill *opt with defaults: FP64, plain map, tolerance 1e-10, 50 passes,
    dC_include_fT1 = 1, no graph, max_steps = 100000, null stream, no workspace, tune = 1. */
 void rteom_default_options(rteom_options* opt);
 
-/* Device bytes rteom_init needs for these sizes and options (no GPU work): the resident
-   integral blocks, three amplitude sets (plus the Anderson history), the scratch of one
-   residual evaluation and, with FP32 or BF16X3 contractions, the converted planes of the
-   constant integral blocks (e.g. 176.5 GiB for FP64 and 241 GiB reduced at o = 36,
-   v = 324, Q = 2000). */
+/* Device bytes rteom_init needs for these sizes and options (no GPU work) under the
+   memory plan it would choose: three amplitude sets (plus T_n for tolerance-driven
+   steps and the Anderson history), the Cholesky vectors and resident integral blocks,
+   and the scratch of one residual evaluation.  OOM if no plan fits mem_limit. */
 rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
                                    int32_t n_chol, int32_t core_orb, int32_t core_spin,
                                    const rteom_options* opt, size_t* bytes);
@@ -194,9 +213,7 @@ rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_
                         int32_t* vir_list);
 
 /* Replace the current amplitudes (host layout above).  Entries of non-existent spin
-   amplitudes are ignored (set to zero).  The same-spin doubles must be antisymmetric
-   in (i,j) and (a,b): the particle-particle ladder and the (me|bf) terms of those
-   blocks read the pairs i<j, a<b only.  Test and benchmark hook. */
+   amplitudes are ignored (set to zero).  Test and benchmark hook. */
 rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double* t2);
 
 /* Copy the current amplitudes to host (layout above). */
@@ -211,14 +228,24 @@ rteom_status rteom_residual(rteom_ctx* ctx, double* r1_out, double* r2_out);
 rteom_status rteom_energy(rteom_ctx* ctx, double* e_out);
 
 /* Floating-point operations of one residual evaluation in this implementation's
-   formulation (real flops: 2 per real MAC, 4 per complex x real, 8 per complex x complex
-   even where the kernels form a complex product from three real ones; the same-spin
-   ladder and (me|bf) terms over their unique pairs).
-   Known from rteom_init on (the contraction plan fixes it). */
+   formulation, over existing spin-orbitals only (real flops: 2 per real MAC, 4 per
+   complex x real, 8 per complex x complex even where the kernels form a complex product
+   from three real ones; same-spin doubles over their unique pairs; the integral slabs
+   rebuilt per residual included).  Known from rteom_init on (the plan fixes it). */
 rteom_status rteom_residual_flops(const rteom_ctx* ctx, double* flops);
 
+/* The memory plan rteom_init chose (all outputs nullable): resident = 1 if the integral
+   blocks are built once, else e_slab = virtual indices per rebuilt slab; ring_cols =
+   occupied columns per block of the ring intermediates; rows = rows per block of
+   expanded same-spin amplitudes; exec_flops = the flops the kernels execute per
+   residual (as rteom_residual_flops, but including the extended space's padding);
+   workspace_bytes = the workspace in use. */
+rteom_status rteom_plan_info(const rteom_ctx* ctx, int32_t* resident, int64_t* e_slab, int64_t* ring_cols,
+                             int64_t* rows, double* exec_flops, size_t* workspace_bytes);
+
 /* Device timing by phase of the hot path: 0 particle-ladder GEMM, 1 o^3 v^3 ring / W / Z
-   GEMMs, 2 other GEMMs, 3 tensor moves, 4 trapezoid update, 5 energy and C(t).  HIP events
+   GEMMs, 2 other GEMMs, 3 tensor moves, 4 trapezoid update, 5 energy and C(t), 6 integral
+   slabs rebuilt from the Cholesky vectors (non-resident plans).  HIP events
    are recorded around every operation of the phases whose bit is set in phase_mask, on the
    context's stream; 0 switches timing off.  For benchmarking and profiling. */
 rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask);

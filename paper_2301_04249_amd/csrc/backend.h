@@ -63,6 +63,7 @@ inline int64_t conv_doubles(int64_t rows, int64_t K) { return (rows * split_ld(K
 // out[idx] = alpha * in[idx] * prod_d scale_d[idx_d] + beta * out[idx] over an
 // nd-dimensional index space; strides per operand.  in may be real while out is
 // complex (then alpha may be complex).  in == out with beta = 0 scales in place.
+// alpha = 0 with beta = 0 writes zeros (whatever in holds).
 struct PermOp {
   int nd = 0;
   int64_t dim[kMaxDims] = {0};
@@ -73,12 +74,34 @@ struct PermOp {
   int beta = 0;
 };
 
-// Layout of an amplitude set (t1 alpha, t1 beta, t2 aa, t2 ab, t2 bb), planar.
+// Index pairs i < j of n indices in lexicographic order: pair (i, j) is number
+// pair_start(i, n) + j - i - 1.
+inline int64_t npairs(int64_t n) { return n * (n - 1) / 2; }
+inline int64_t pair_start(int64_t i, int64_t n) { return i * (2 * n - i - 1) / 2; }
+
+// Layout of an amplitude set, planar (all real parts, then all imaginary parts):
+//   t1 alpha [no][nv], t1 beta [no][nv],
+//   t2 alpha-alpha [npairs(no)][npairs(nv)]  (t_ijab for i < j, a < b),
+//   t2 beta-beta   [npairs(no)][npairs(nv)],
+//   t2 alpha-beta  [no][no][nv][nv].
+// The same-spin doubles are antisymmetric in (i, j) and in (a, b); only their
+// unique elements are stored.
 struct AmpLayout {
   int64_t no = 0, nv = 0;
   int64_t n1() const { return no * nv; }
-  int64_t n2() const { return no * no * nv * nv; }
-  int64_t size() const { return 2 * n1() + 3 * n2(); }
+  int64_t npo() const { return npairs(no); }
+  int64_t npv() const { return npairs(nv); }
+  int64_t nss() const { return npo() * npv(); }          // one same-spin block
+  int64_t nab() const { return no * no * nv * nv; }      // the alpha-beta block
+  int64_t off_ss(int s) const { return 2 * n1() + s * nss(); }
+  int64_t off_ab() const { return 2 * n1() + 2 * nss(); }
+  int64_t size() const { return 2 * n1() + 2 * nss() + nab(); }
+};
+
+// Pair tables on the device: for pair p, first[p] < second[p] (int32).
+struct PairTables {
+  const int32_t* oi = nullptr; const int32_t* oj = nullptr;   // occupied pairs, [npairs(no)]
+  const int32_t* va = nullptr; const int32_t* vb = nullptr;   // virtual pairs, [npairs(nv)]
 };
 
 // Per-spin occupancy masks and Fock diagonals (device vectors), used to zero
@@ -98,6 +121,7 @@ struct SpinVectors {
 //   x' = 0 where the spin-orbital does not exist;  *delta = max |x' - x|.
 struct UpdateOp {
   AmpLayout lay;
+  PairTables pt;
   double* x_re = nullptr; double* x_im = nullptr;
   const double* r_re = nullptr; const double* r_im = nullptr;
   double* rhs_re = nullptr; double* rhs_im = nullptr;
@@ -108,25 +132,42 @@ struct UpdateOp {
   double* delta = nullptr;  // device double, max-reduced (caller zeroes it)
 };
 
-// Antisymmetric pair storage of same-spin blocks.  x holds nblk blocks (x_bs
-// doubles apart) of shape [n1][n1][rest]; rest is [n2][n2] (pair2 = 1) or n2
-// plain elements (pair2 = 0).  y holds the packed form [np1][nq] per block (y_bs
-// apart) over index pairs p = (i < j) and, with pair2, q = (a < b), both in
-// lexicographic order: np1 = n1 (n1 - 1) / 2, nq = n2 (n2 - 1) / 2 or n2.
-//   pack   (mode 0): y[p][q] = alpha (x[i][j][c] - anti x[j][i][c]), c = (a, b) or q
-//   unpack (mode 1): x[i][j][c] = alpha s y[p][q] + beta x[i][j][c] for i != j (and
-//                    a != b), s = -1 per swapped pair; elements with i == j (or
-//                    a == b) become beta x.
-// x and y are planar complex when x_im / y_im are set (both or neither).
-struct PairOp {
-  int64_t n1 = 0, n2 = 0, nblk = 1;
-  int pair2 = 1;
-  double* x_re = nullptr; double* x_im = nullptr; int64_t x_bs = 0;
-  double* y_re = nullptr; double* y_im = nullptr; int64_t y_bs = 0;
-  double alpha = 1.0;
-  int anti = 0;
+// Same-spin doubles between antisymmetric pair storage y [npairs(n1)][npairs(n2)] (planar
+// complex when y_im is set, else real) and full storage.  x is a block of a full tensor
+// [n1][n1][n2][n2] holding rows i0 .. i0+ci-1 and columns j0 .. j0+cj-1 of the first two
+// indices, row-major [ci][cj][n2][n2] (x_im with y_im).
+//   kExpand:     x[i][j][a][b] = alpha s y[pair(i,j)][pair(a,b)] + beta x  (s = -1 per
+//                swapped pair; 0 where i = j or a = b)
+//   kAccum:      y[pair(i,j)][pair(a,b)] += alpha (sum over the block's elements that map
+//                there): the antisymmetric part of x -- with anti1 the element (i,j) adds
+//                to pair (i,j) and with a minus sign to pair (j,i) (P(ij)); without it x
+//                is antisymmetric in (i,j) already and only i < j is read.  anti2 likewise
+//                for (a,b).  Every pair is written by one thread (no atomics).
+//   kAccumRows:  x is [cp][n2][n2] over pairs p0 .. p0+cp-1 of the first index:
+//                y[p][pair(a,b)] += alpha (x[p][a][b] - anti2 x[p][b][a])
+//   kT1T1:       y[p][q] = beta y + alpha (u_ia u_jb - u_ib u_ja), u = [n1][n2] complex
+//                (u_re/u_im), (i,j) = pair p, (a,b) = pair q
+//   kMask:       y[p][q] *= m1[i] m1[j] m2[a] m2[b]
+//   kPackSlab:   integral slab x [ce][n1][rest] holding rows e0 .. e0+ce-1 of a real
+//                [n1][n1][rest] tensor (rest = n2 n2 with pair2, else n2); y gets the
+//                pairs (e < f) with e in the slab, in order, rows [npairs-range][nq]:
+//                pair2: y[.][pair(a,b)] = alpha (x[e][f][a][b] - x[e][f][b][a]),
+//                else   y[.][c] = alpha x[e][f][c].
+struct SsOp {
+  enum Mode { kExpand = 0, kAccum = 1, kAccumRows = 2, kT1T1 = 3, kMask = 4, kPackSlab = 5 };
   int mode = 0;
+  int64_t n1 = 0, n2 = 0;
+  int64_t i0 = 0, ci = 0, j0 = 0, cj = 0;   // block of x (kExpand, kAccum); p0, cp in i0, ci for kAccumRows;
+                                            // e0, ce in i0, ci for kPackSlab
+  int pair2 = 1;
+  int anti1 = 1, anti2 = 1;
+  double alpha = 1.0;
   int beta = 0;
+  double* x_re = nullptr; double* x_im = nullptr;
+  double* y_re = nullptr; double* y_im = nullptr;
+  const double* u_re = nullptr; const double* u_im = nullptr;
+  const double* m1 = nullptr; const double* m2 = nullptr;
+  PairTables pt;   // tables of n1 (oi/oj) and n2 (va/vb) pairs
 };
 
 // E(T) = sum f_ia t_ia + 1/4 sum <ij||ab> t_ijab + 1/2 sum <ij||ab> t_ia t_jb in
@@ -151,7 +192,8 @@ enum Phase {
   kPhaseMove = 3,     // permutes, copies, scaling
   kPhaseUpdate = 4,   // fused trapezoid update
   kPhaseEnergy = 5,   // energy reduction and C(t) append
-  kNumPhases = 6
+  kPhaseBuild = 6,    // integral slabs rebuilt from the Cholesky vectors
+  kNumPhases = 7
 };
 
 class Backend {
@@ -179,7 +221,7 @@ class Backend {
   virtual void fill(double* p, int64_t n, double v) = 0;
   virtual void gemm(const GemmOp& op) = 0;
   virtual void permute(const PermOp& op) = 0;
-  virtual void pairs(const PairOp& op) = 0;
+  virtual void ss(const SsOp& op) = 0;
   virtual void update(const UpdateOp& op) = 0;
   virtual void energy(const EnergyOp& op) = 0;
   // With k = *step (device): C[k+1] = C[k] + i h (E[k] + e_next), E[k+1] = e_next,

@@ -816,6 +816,7 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
     const double xi = p.ii ? p.ii[io] : 0.0;
     double vr = s * (p.ar * xr - p.ai * xi);
     double vi = s * (p.ar * xi + p.ai * xr);
+    if (p.ar == 0.0 && p.ai == 0.0) vr = vi = 0.0;   // a zero fill whatever the input holds
     if (p.beta) {
       vr += p.orr[oo];
       if (p.oi) vi += p.oi[oo];
@@ -825,80 +826,38 @@ __global__ __launch_bounds__(256) void permute_kernel(PermArgs p) {
   }
 }
 
-// Antisymmetric pair storage (PairOp): pairs p = (i < j) of n in lexicographic
-// order start at pair_start(i, n) = i (2n - i - 1) / 2.
-struct PairArgs {
-  int64_t n1, n2, np1, nq, rows;
-  int pair2, anti, beta;
-  double* xr; double* xi; int64_t xbs;
-  double* yr; double* yi; int64_t ybs;
+// Same-spin pair storage (SsOp): pairs p = (i < j) of n in lexicographic order
+// start at pstart(i, n) = i (2n - i - 1) / 2.
+struct SsArgs {
+  int64_t n1, n2, np2, i0, ci, j0, cj, rows;
+  int pair2, anti1, anti2, beta;
   double alpha;
+  double* xr; double* xi;
+  double* yr; double* yi;
+  const double* ur; const double* ui;
+  const double* m1; const double* m2;
+  const int32_t* oi; const int32_t* oj; const int32_t* va; const int32_t* vb;
 };
 
-__device__ inline int64_t pair_start(int64_t i, int64_t n) { return i * (2 * n - i - 1) / 2; }
+__device__ inline int64_t pstart(int64_t i, int64_t n) { return i * (2 * n - i - 1) / 2; }
+__device__ inline int64_t pidx(int64_t i, int64_t j, int64_t n) { return pstart(i, n) + j - i - 1; }
 
-// (i, j) of pair p: the square-root estimate of i, corrected by exact integer tests
-__device__ inline void pair_of(int64_t p, int64_t n, int64_t& i, int64_t& j) {
-  const double b = 2.0 * (double)n - 1.0;
-  int64_t k = (int64_t)floor(0.5 * (b - sqrt(fmax(b * b - 8.0 * (double)p, 0.0))));
-  k = k < 0 ? 0 : (k > n - 2 ? n - 2 : k);
-  while (k > 0 && pair_start(k, n) > p) --k;
-  while (k < n - 2 && pair_start(k + 1, n) <= p) ++k;
-  i = k;
-  j = p - pair_start(k, n) + k + 1;
-}
-
-// One packed row per iteration: (block, p, a) with pair2, else (block, p).
-__global__ __launch_bounds__(256) void pair_pack(PairArgs g) {
-  const int64_t rest = g.pair2 ? g.n2 * g.n2 : g.n2;
+// kExpand: one row (ii, jj, a) of the full block per iteration, b across the threads.
+__global__ __launch_bounds__(256) void ss_expand(SsArgs g) {
   for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
-    int64_t r = row, a = 0;
-    if (g.pair2) { a = r % g.n2; r /= g.n2; }
-    const int64_t p = r % g.np1, blk = r / g.np1;
-    int64_t i, j;
-    pair_of(p, g.n1, i, j);
-    const int64_t xij = blk * g.xbs + (i * g.n1 + j) * rest, xji = blk * g.xbs + (j * g.n1 + i) * rest;
-    const int64_t yo = blk * g.ybs + p * g.nq + (g.pair2 ? pair_start(a, g.n2) - a - 1 : 0);
-    const int64_t c0 = g.pair2 ? a * g.n2 : 0;
-    const int64_t lo = g.pair2 ? a + 1 : 0;
-    for (int64_t b = lo + threadIdx.x; b < g.n2; b += blockDim.x) {
-      const int64_t c = c0 + b;
-      double vr = g.xr[xij + c], vi = g.xi ? g.xi[xij + c] : 0.0;
-      if (g.anti) {
-        vr -= g.xr[xji + c];
-        if (g.xi) vi -= g.xi[xji + c];
-      }
-      g.yr[yo + b] = g.alpha * vr;
-      if (g.yi) g.yi[yo + b] = g.alpha * vi;
-    }
-  }
-}
-
-// One full row per iteration: (block, i, j, a) with pair2, else (block, i, j).
-__global__ __launch_bounds__(256) void pair_unpack(PairArgs g) {
-  const int64_t rest = g.pair2 ? g.n2 * g.n2 : g.n2;
-  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
-    int64_t r = row, a = 0;
-    if (g.pair2) { a = r % g.n2; r /= g.n2; }
-    const int64_t j = r % g.n1;
-    r /= g.n1;
-    const int64_t i = r % g.n1, blk = r / g.n1;
-    const int64_t xo = blk * g.xbs + (i * g.n1 + j) * rest + (g.pair2 ? a * g.n2 : 0);
-    const int64_t lo = i < j ? i : j, hi = i < j ? j : i;
-    const int64_t yo = blk * g.ybs + (pair_start(lo, g.n1) + hi - lo - 1) * g.nq;
-    const double sij = i < j ? 1.0 : -1.0;
+    const int64_t a = row % g.n2, r = row / g.n2, jj = r % g.cj, ii = r / g.cj;
+    const int64_t i = g.i0 + ii, j = g.j0 + jj;
+    const int64_t xo = row * g.n2;
+    const bool diag = i == j;
+    const int64_t p = diag ? 0 : pidx(i < j ? i : j, i < j ? j : i, g.n1);
+    const double si = i < j ? g.alpha : -g.alpha;
     for (int64_t b = threadIdx.x; b < g.n2; b += blockDim.x) {
       double vr = 0.0, vi = 0.0;
-      if (i != j && (!g.pair2 || a != b)) {
-        int64_t q = b;
-        double sg = sij;
-        if (g.pair2) {
-          const int64_t qa = a < b ? a : b, qb = a < b ? b : a;
-          q = pair_start(qa, g.n2) + qb - qa - 1;
-          if (b < a) sg = -sg;
-        }
-        vr = g.alpha * sg * g.yr[yo + q];
-        if (g.yi) vi = g.alpha * sg * g.yi[yo + q];
+      if (!diag && a != b) {
+        const int64_t q = p * g.np2 + (a < b ? pidx(a, b, g.n2) : pidx(b, a, g.n2));
+        const double sg = a < b ? si : -si;
+        vr = sg * g.yr[q];
+        if (g.yi) vi = sg * g.yi[q];
       }
       if (g.beta) {
         vr += g.xr[xo + b];
@@ -906,6 +865,123 @@ __global__ __launch_bounds__(256) void pair_unpack(PairArgs g) {
       }
       g.xr[xo + b] = vr;
       if (g.xi) g.xi[xo + b] = vi;
+    }
+  }
+}
+
+// kAccum: one row (ii, jj, a) of the block per iteration, b > a across the threads.
+// A row with i < j owns pair (i, j) and adds the partner row (j, i) when the block
+// holds it (anti1); a row with i > j writes pair (j, i) with a minus sign only when
+// the block does not hold (j, i).  Every pair element has one writer.
+__global__ __launch_bounds__(256) void ss_accum(SsArgs g) {
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    const int64_t a = row % g.n2, r = row / g.n2, jj = r % g.cj, ii = r / g.cj;
+    const int64_t i = g.i0 + ii, j = g.j0 + jj;
+    if (i == j) continue;
+    const bool partner_in = j >= g.i0 && j < g.i0 + g.ci && i >= g.j0 && i < g.j0 + g.cj;
+    if (i > j && (!g.anti1 || partner_in)) continue;
+    const bool lo = i < j;
+    const int64_t p = lo ? pidx(i, j, g.n1) : pidx(j, i, g.n1);
+    const double sgn = lo ? g.alpha : -g.alpha;
+    const bool partner = lo && g.anti1 && partner_in;
+    const int64_t xo = ((ii * g.cj + jj) * g.n2 + a) * g.n2;
+    const int64_t xq = partner ? (((j - g.i0) * g.cj + (i - g.j0)) * g.n2 + a) * g.n2 : 0;
+    const int64_t xo2 = ((ii * g.cj + jj) * g.n2) * g.n2 + a;    // x[ii][jj][.][a]
+    const int64_t xq2 = partner ? (((j - g.i0) * g.cj + (i - g.j0)) * g.n2) * g.n2 + a : 0;
+    const int64_t yo = p * g.np2 + pidx(a, a + 1, g.n2) - (a + 1);   // + b gives pair (a, b)
+    for (int64_t b = a + 1 + threadIdx.x; b < g.n2; b += blockDim.x) {
+      double vr = g.xr[xo + b], vi = g.xi ? g.xi[xo + b] : 0.0;
+      if (g.anti2) {
+        vr -= g.xr[xo2 + b * g.n2];
+        if (g.xi) vi -= g.xi[xo2 + b * g.n2];
+      }
+      if (partner) {
+        vr -= g.xr[xq + b];
+        if (g.xi) vi -= g.xi[xq + b];
+        if (g.anti2) {
+          vr += g.xr[xq2 + b * g.n2];
+          if (g.xi) vi += g.xi[xq2 + b * g.n2];
+        }
+      }
+      g.yr[yo + b] += sgn * vr;
+      if (g.yi) g.yi[yo + b] += sgn * vi;
+    }
+  }
+}
+
+// kAccumRows: rows (pp, a), b > a across the threads.
+__global__ __launch_bounds__(256) void ss_accum_rows(SsArgs g) {
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    const int64_t a = row % g.n2, pp = row / g.n2;
+    const int64_t xo = (pp * g.n2 + a) * g.n2, xo2 = pp * g.n2 * g.n2 + a;
+    const int64_t yo = (g.i0 + pp) * g.np2 + pidx(a, a + 1, g.n2) - (a + 1);
+    for (int64_t b = a + 1 + threadIdx.x; b < g.n2; b += blockDim.x) {
+      double vr = g.xr[xo + b], vi = g.xi ? g.xi[xo + b] : 0.0;
+      if (g.anti2) {
+        vr -= g.xr[xo2 + b * g.n2];
+        if (g.xi) vi -= g.xi[xo2 + b * g.n2];
+      }
+      g.yr[yo + b] += g.alpha * vr;
+      if (g.yi) g.yi[yo + b] += g.alpha * vi;
+    }
+  }
+}
+
+// kT1T1 and kMask: rows (p, a) of the pair block, b > a across the threads.
+__global__ __launch_bounds__(256) void ss_pairwise(SsArgs g, int mask) {
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    const int64_t a = row % g.n2, p = row / g.n2;
+    const int64_t i = g.oi[p], j = g.oj[p];
+    const int64_t yo = p * g.np2 + pidx(a, a + 1, g.n2) - (a + 1);
+    if (mask) {
+      const double ma = g.m1[i] * g.m1[j] * g.m2[a];
+      for (int64_t b = a + 1 + threadIdx.x; b < g.n2; b += blockDim.x) {
+        const double m = ma * g.m2[b];
+        g.yr[yo + b] *= m;
+        if (g.yi) g.yi[yo + b] *= m;
+      }
+      continue;
+    }
+    const double iar = g.ur[i * g.n2 + a], iai = g.ui[i * g.n2 + a];
+    const double jar = g.ur[j * g.n2 + a], jai = g.ui[j * g.n2 + a];
+    for (int64_t b = a + 1 + threadIdx.x; b < g.n2; b += blockDim.x) {
+      const double jbr = g.ur[j * g.n2 + b], jbi = g.ui[j * g.n2 + b];
+      const double ibr = g.ur[i * g.n2 + b], ibi = g.ui[i * g.n2 + b];
+      const double vr = (iar * jbr - iai * jbi) - (ibr * jar - ibi * jai);
+      const double vi = (iar * jbi + iai * jbr) - (ibr * jai + ibi * jar);
+      double yr = g.alpha * vr, yi = g.alpha * vi;
+      if (g.beta) {
+        yr += g.yr[yo + b];
+        yi += g.yi[yo + b];
+      }
+      g.yr[yo + b] = yr;
+      g.yi[yo + b] = yi;
+    }
+  }
+}
+
+// kPackSlab: rows (ee, f) (and a with pair2) of the slab; pairs (e < f) only.
+__global__ __launch_bounds__(256) void ss_pack_slab(SsArgs g) {
+  const int64_t rest = g.pair2 ? g.n2 * g.n2 : g.n2, nq = g.pair2 ? g.np2 : g.n2;
+  const int64_t base = pstart(g.i0, g.n1);
+  for (int64_t row = blockIdx.x; row < g.rows; row += gridDim.x) {
+    int64_t r = row, a = 0;
+    if (g.pair2) { a = r % g.n2; r /= g.n2; }
+    const int64_t f = r % g.n1, ee = r / g.n1, e = g.i0 + ee;
+    if (f <= e) continue;
+    const int64_t p = pidx(e, f, g.n1) - base;
+    const int64_t xo = (ee * g.n1 + f) * rest;
+    if (g.pair2) {
+      const int64_t yo = p * nq + pidx(a, a + 1, g.n2) - (a + 1);
+      for (int64_t b = a + 1 + threadIdx.x; b < g.n2; b += blockDim.x) {
+        g.yr[yo + b] = g.alpha * (g.xr[xo + a * g.n2 + b] - g.xr[xo + b * g.n2 + a]);
+        if (g.yi) g.yi[yo + b] = g.alpha * (g.xi[xo + a * g.n2 + b] - g.xi[xo + b * g.n2 + a]);
+      }
+    } else {
+      for (int64_t c = threadIdx.x; c < g.n2; c += blockDim.x) {
+        g.yr[p * nq + c] = g.alpha * g.xr[xo + c];
+        if (g.yi) g.yi[p * nq + c] = g.alpha * g.xi[xo + c];
+      }
     }
   }
 }
@@ -944,6 +1020,7 @@ __global__ __launch_bounds__(256) void permute_tiled(PermArgs p, int din, int do
         const double xr = p.ir[o], xi = p.ii ? p.ii[o] : 0.0;
         vr = sv * (p.ar * xr - p.ai * xi);
         vi = sv * (p.ar * xi + p.ai * xr);
+        if (p.ar == 0.0 && p.ai == 0.0) vr = vi = 0.0;
       }
       tr[ty + 8 * j][tx] = vr;
       ti[ty + 8 * j][tx] = vi;
@@ -983,7 +1060,8 @@ __device__ inline double wave_sum(double v) {
 }
 
 struct UpdArgs {
-  int64_t no, nv, n1, n2, total;
+  int64_t no, nv, n1, nss, npv, off_ab, total;
+  const int32_t* oi; const int32_t* oj; const int32_t* va; const int32_t* vb;
   double* xr; double* xi;
   const double* rr; const double* ri;
   double* hr_; double* hi_;
@@ -1004,16 +1082,21 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs u) {
       const int64_t r = k - s * u.n1, i = r / u.nv, a = r - i * u.nv;
       mask = u.mo[s][i] * u.mv[s][a];
       dd = u.fo[s][i] - u.fv[s][a];
-    } else {
+    } else if (k < u.off_ab) {
+      // same-spin pair element (i < j, a < b) of block s
       const int64_t k2 = k - 2 * u.n1;
-      const int blk = (int)(k2 / u.n2);
-      const int s1 = blk == 2, s2 = blk != 0;
-      int64_t r = k2 - blk * u.n2;
+      const int s = k2 >= u.nss;
+      const int64_t r = k2 - s * u.nss, p = r / u.npv, q = r - p * u.npv;
+      const int64_t i = u.oi[p], j = u.oj[p], a = u.va[q], b = u.vb[q];
+      mask = u.mo[s][i] * u.mo[s][j] * u.mv[s][a] * u.mv[s][b];
+      dd = u.fo[s][i] + u.fo[s][j] - u.fv[s][a] - u.fv[s][b];
+    } else {
+      int64_t r = k - u.off_ab;
       const int64_t b = r % u.nv; r /= u.nv;
       const int64_t a = r % u.nv; r /= u.nv;
       const int64_t j = r % u.no, i = r / u.no;
-      mask = u.mo[s1][i] * u.mo[s2][j] * u.mv[s1][a] * u.mv[s2][b];
-      dd = u.fo[s1][i] + u.fo[s2][j] - u.fv[s1][a] - u.fv[s2][b];
+      mask = u.mo[0][i] * u.mo[1][j] * u.mv[0][a] * u.mv[1][b];
+      dd = u.fo[0][i] + u.fo[1][j] - u.fv[0][a] - u.fv[1][b];
     }
     const double xr = u.xr[k], xi = u.xi[k], rr = u.rr[k], ri = u.ri[k];
     double nr, ni;
@@ -1069,7 +1152,7 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs u) {
 }
 
 struct EnArgs {
-  int64_t no, nv, n1, n2;
+  int64_t no, nv, n1, npv, off_aa, off_bb, off_ab;
   const double* xr; const double* xi;
   const double* jov;
   const double* fov0; const double* fov1; int64_t ld;
@@ -1085,8 +1168,8 @@ __global__ __launch_bounds__(256) void energy_pass1(EnArgs e) {
   const int64_t total = e.no * e.nv * e.no * e.nv;
   const double* T1r = e.xr;
   const double* T1i = e.xi;
-  const double* Tr = e.xr + 2 * e.n1;
-  const double* Ti = e.xi + 2 * e.n1;
+  const double* Tr = e.xr + e.off_ab;
+  const double* Ti = e.xi + e.off_ab;
   double accr = 0.0, acci = 0.0;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
@@ -1096,8 +1179,14 @@ __global__ __launch_bounds__(256) void energy_pass1(EnArgs e) {
     const int64_t a = r % e.nv; const int64_t i = r / e.nv;
     const double J = e.jov[t];
     const int64_t p = ((i * e.no + j) * e.nv + a) * e.nv + b;
-    double wr = 0.5 * (Tr[p] + Tr[2 * e.n2 + p]) + Tr[e.n2 + p];
-    double wi = 0.5 * (Ti[p] + Ti[2 * e.n2 + p]) + Ti[e.n2 + p];
+    double wr = Tr[p], wi = Ti[p];
+    // 1/2 (t_aa + t_bb) with the same-spin elements read from pair storage
+    if (i != j && a != b) {
+      const double sg = 0.5 * (i < j ? 1.0 : -1.0) * (a < b ? 1.0 : -1.0);
+      const int64_t q = pidx(i < j ? i : j, i < j ? j : i, e.no) * e.npv + pidx(a < b ? a : b, a < b ? b : a, e.nv);
+      wr += sg * (e.xr[e.off_aa + q] + e.xr[e.off_bb + q]);
+      wi += sg * (e.xi[e.off_aa + q] + e.xi[e.off_bb + q]);
+    }
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
       const int64_t o = s * e.n1;
@@ -1761,29 +1850,40 @@ class HipBackend : public Backend {
     end();
   }
 
-  void pairs(const PairOp& op) override {
-    PairArgs g;
-    g.n1 = op.n1; g.n2 = op.n2; g.pair2 = op.pair2; g.anti = op.anti; g.beta = op.beta;
-    g.np1 = op.n1 * (op.n1 - 1) / 2;
-    g.nq = op.pair2 ? op.n2 * (op.n2 - 1) / 2 : op.n2;
-    g.xr = op.x_re; g.xi = op.x_im; g.xbs = op.x_bs;
-    g.yr = op.y_re; g.yi = op.y_im; g.ybs = op.y_bs;
-    g.alpha = op.alpha;
-    g.rows = op.mode == 0 ? op.nblk * g.np1 * (op.pair2 ? op.n2 : 1)
-                          : op.nblk * op.n1 * op.n1 * (op.pair2 ? op.n2 : 1);
+  void ss(const SsOp& op) override {
+    SsArgs g;
+    g.n1 = op.n1; g.n2 = op.n2; g.np2 = op.n2 * (op.n2 - 1) / 2;
+    g.i0 = op.i0; g.ci = op.ci; g.j0 = op.j0; g.cj = op.cj;
+    g.pair2 = op.pair2; g.anti1 = op.anti1; g.anti2 = op.anti2; g.beta = op.beta; g.alpha = op.alpha;
+    g.xr = op.x_re; g.xi = op.x_im; g.yr = op.y_re; g.yi = op.y_im;
+    g.ur = op.u_re; g.ui = op.u_im; g.m1 = op.m1; g.m2 = op.m2;
+    g.oi = op.pt.oi; g.oj = op.pt.oj; g.va = op.pt.va; g.vb = op.pt.vb;
+    const int64_t np1 = op.n1 * (op.n1 - 1) / 2;
+    switch (op.mode) {
+      case SsOp::kExpand: case SsOp::kAccum: g.rows = op.ci * op.cj * op.n2; break;
+      case SsOp::kAccumRows: g.rows = op.ci * op.n2; break;
+      case SsOp::kT1T1: case SsOp::kMask: g.rows = np1 * op.n2; break;
+      default: g.rows = op.ci * op.n1 * (op.pair2 ? op.n2 : 1); break;
+    }
     if (g.rows <= 0 || op.n2 <= 0) return;
-    if (op.mode == 0 && op.n1 < 2) return;
     begin();
     const unsigned grid = (unsigned)std::min<int64_t>(g.rows, 1 << 20);
-    if (op.mode == 0) pair_pack<<<grid, 256, 0, stream_>>>(g);
-    else pair_unpack<<<grid, 256, 0, stream_>>>(g);
-    launched(op.mode == 0 ? "pair pack" : "pair unpack");
+    switch (op.mode) {
+      case SsOp::kExpand: ss_expand<<<grid, 256, 0, stream_>>>(g); launched("pair expand"); break;
+      case SsOp::kAccum: ss_accum<<<grid, 256, 0, stream_>>>(g); launched("pair accumulate"); break;
+      case SsOp::kAccumRows: ss_accum_rows<<<grid, 256, 0, stream_>>>(g); launched("pair accumulate rows"); break;
+      case SsOp::kT1T1: ss_pairwise<<<grid, 256, 0, stream_>>>(g, 0); launched("pair t1 t1"); break;
+      case SsOp::kMask: ss_pairwise<<<grid, 256, 0, stream_>>>(g, 1); launched("pair mask"); break;
+      default: ss_pack_slab<<<grid, 256, 0, stream_>>>(g); launched("pair pack"); break;
+    }
     end();
   }
 
   void update(const UpdateOp& u) override {
     UpdArgs a;
-    a.no = u.lay.no; a.nv = u.lay.nv; a.n1 = u.lay.n1(); a.n2 = u.lay.n2(); a.total = u.lay.size();
+    a.no = u.lay.no; a.nv = u.lay.nv; a.n1 = u.lay.n1(); a.nss = u.lay.nss(); a.npv = u.lay.npv();
+    a.off_ab = u.lay.off_ab(); a.total = u.lay.size();
+    a.oi = u.pt.oi; a.oj = u.pt.oj; a.va = u.pt.va; a.vb = u.pt.vb;
     a.xr = u.x_re; a.xi = u.x_im; a.rr = u.r_re; a.ri = u.r_im; a.hr_ = u.rhs_re; a.hi_ = u.rhs_im;
     a.h = u.h; a.mode = u.mode; a.start = u.start;
     for (int s = 0; s < 2; ++s) {
@@ -1798,7 +1898,8 @@ class HipBackend : public Backend {
 
   void energy(const EnergyOp& op) override {
     EnArgs e;
-    e.no = op.lay.no; e.nv = op.lay.nv; e.n1 = op.lay.n1(); e.n2 = op.lay.n2();
+    e.no = op.lay.no; e.nv = op.lay.nv; e.n1 = op.lay.n1(); e.npv = op.lay.npv();
+    e.off_aa = op.lay.off_ss(0); e.off_bb = op.lay.off_ss(1); e.off_ab = op.lay.off_ab();
     e.xr = op.x_re; e.xi = op.x_im; e.jov = op.jov;
     e.fov0 = op.fov[0]; e.fov1 = op.fov[1]; e.ld = op.fov_ld; e.ft1 = op.include_ft1;
     e.part = op.partial; e.out = op.e_out;

@@ -37,10 +37,17 @@ View reorder(const View& v, std::initializer_list<int> order) {
   for (int o : order) {
     r.dim[d] = v.dim[o];
     r.str[d] = v.str[o];
+    r.frac[d] = v.frac[o];
     ++d;
   }
   r.nd = d;
   return r;
+}
+
+View with_frac(View v, std::initializer_list<double> f) {
+  int d = 0;
+  for (double x : f) v.frac[d++] = x;
+  return v;
 }
 
 View block(const View& v, std::initializer_list<int64_t> lo, std::initializer_list<int64_t> n) {
@@ -67,6 +74,7 @@ View diagonal(const View& v, int d0, int d1) {
     if (d == d1) continue;
     r.dim[k] = v.dim[d];
     r.str[k] = (d == d0) ? v.str[d0] + v.str[d1] : v.str[d];
+    r.frac[k] = (d == d0) ? std::min(v.frac[d0], v.frac[d1]) : v.frac[d];
     ++k;
   }
   r.nd = k;
@@ -169,10 +177,10 @@ void Engine::add(const View& out, const View& in, double alpha_re, double alpha_
   }
 }
 
-void Engine::pairs(const PairOp& op) {
+void Engine::ss(const SsOp& op) {
   if (dry) return;
   be->set_phase(kPhaseMove);
-  be->pairs(op);
+  be->ss(op);
   be->set_phase(phase);
 }
 
@@ -402,6 +410,17 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   }
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;
+  // the method's own share: every letter scaled by the smallest existing-index fraction
+  // any operand gives it
+  double fa = f;
+  for (char c : Bg + Mg + Ng + Kg) {
+    double fr = 1.0;
+    int p;
+    if ((p = pos(sp.a, c)) >= 0) fr = std::min(fr, A.frac[p]);
+    if ((p = pos(sp.b, c)) >= 0) fr = std::min(fr, B.frac[p]);
+    if ((p = pos(sp.c, c)) >= 0) fr = std::min(fr, C.frac[p]);
+    fa *= fr;
+  }
 #ifdef RTEOM_PLAN_TRACE
   std::fprintf(stderr, "PLAN %-22s M=%lld N=%lld K=%lld batch=%lld split=%d A%s%s B%s%s ctemp=%d flops=%.3g arena=%.2fGiB\n",
                spec_str, (long long)op.M, (long long)op.N, (long long)op.K, (long long)op.batch, op.splitk,
@@ -410,6 +429,8 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
 #endif
   flops += f;
   phase_flops[phase] += f;
+  alg_flops += fa;
+  alg_phase_flops[phase] += fa;
   if (op.M > 0 && op.N > 0 && op.batch > 0 && !dry) {
     if (op.K == 0) {
       // empty sum: C = beta * C

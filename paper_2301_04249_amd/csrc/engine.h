@@ -16,13 +16,17 @@ struct Error : std::runtime_error {
   Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
 };
 
-// A strided view of a real or planar-complex tensor in device memory.
+// A strided view of a real or planar-complex tensor in device memory.  frac[d] is the
+// fraction of dimension d's indices that exist in the method (the extended orbital space
+// pads each spin's occupied and virtual range to a common size); the flop count of the
+// method's own work scales each summed, row or column index by it.
 struct View {
   double* re = nullptr;
   double* im = nullptr;
   int nd = 0;
   int64_t dim[kMaxDims] = {0};
   int64_t str[kMaxDims] = {0};
+  double frac[kMaxDims] = {1, 1, 1, 1, 1, 1};
   bool cplx() const { return im != nullptr; }
   int64_t numel() const {
     int64_t n = 1;
@@ -39,6 +43,8 @@ View reorder(const View& v, std::initializer_list<int> order);
 View block(const View& v, std::initializer_list<int64_t> lo, std::initializer_list<int64_t> n);
 // Diagonal of dimensions d0 and d1 (merged into d0, d1 removed).
 View diagonal(const View& v, int d0, int d1);
+// The same view with existing-index fractions set per dimension.
+View with_frac(View v, std::initializer_list<double> f);
 
 // Bump allocator over one device buffer; temporaries are released in LIFO order.
 // All device work is ordered on one stream, so memory released after an
@@ -74,8 +80,10 @@ class Engine {
   Backend* be = nullptr;
   Arena* scratch = nullptr;
   int prec = 0;
-  double flops = 0.0;       // accumulated GEMM flops (real-flop convention)
+  double flops = 0.0;       // accumulated GEMM flops (real-flop convention), as executed
   double phase_flops[kNumPhases] = {0};
+  double alg_flops = 0.0;   // the same over existing spin-orbitals only (no padding)
+  double alg_phase_flops[kNumPhases] = {0};
   int phase = kPhaseGemm;
   void set_phase(int ph) {
     phase = ph;
@@ -92,8 +100,8 @@ class Engine {
   // out = alpha * in + beta * out (same shape), optional per-dimension scale vectors
   void add(const View& out, const View& in, double alpha_re, double alpha_im, int beta,
            const double* const* scale = nullptr);
-  // pack / unpack antisymmetric pair storage (PairOp)
-  void pairs(const PairOp& op);
+  // same-spin pair storage operations (SsOp)
+  void ss(const SsOp& op);
   // out *= prod_d scale_d (in place)
   void scale(const View& out, const double* const* scale);
   View temp(std::initializer_list<int64_t> dims, bool cplx);

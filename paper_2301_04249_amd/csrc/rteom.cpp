@@ -8,7 +8,8 @@
 //   spin; per-spin masks zero the amplitudes of spin-orbitals that do not exist
 //   (for a beta hole: beta amplitudes with occupied index c, alpha amplitudes
 //   with virtual index c).  Integrals are spin free, so all three T2 blocks
-//   (aa, ab, bb) share one shape and one set of integral blocks.
+//   (aa, ab, bb) share one set of integral blocks.  The same-spin doubles are
+//   stored over their unique pairs (i < j, a < b); the alpha-beta block in full.
 // * Residual.  R_x = <Phi_x| e^{-T} H_N e^{T} |Phi> is evaluated in the
 //   T1-similarity-transformed ("dressed") form: e^{-T1} H e^{T1} has the
 //   Cholesky vectors L~ = (1 - t) L (1 + t) (t: the virtual-by-occupied T1
@@ -17,6 +18,13 @@
 //   dt2eom).  The pp-ladder keeps the real (ae|bf) integrals; the T1 part of the
 //   dressed virtual vectors becomes the o^3 v^3 "Z" terms and an o^4 v^2 term.
 //   Coulomb-type ring terms are factorised through D^Q_ia = sum_me T_imae L^Q_me.
+// * Memory.  Every intermediate that grows like o^2 v^2 or faster is produced in
+//   blocks when the whole would not fit: the ring intermediates W[(m,e),(b,j)] in
+//   blocks of j, expanded same-spin amplitudes in blocks of rows, and -- when they
+//   cannot stay resident -- (ae|bf), (me|bf) and their pair forms rebuilt from the
+//   Cholesky vectors in slabs of e for every residual.  A plan chosen at init
+//   (the largest blocks that keep the workspace within the memory limit) fixes
+//   the block sizes; the arithmetic of every element is the same for any plan.
 // * Step.  Implicit trapezoid (Eq. trapzrule) with fixed-point passes; three
 //   amplitude-sized buffers (iterate X, rhs, residual R) as in Table 2's three
 //   timeline tensors.  C(t) accumulates i E(T) with the same trapezoid weights.
@@ -41,6 +49,18 @@ Backend* make_host_backend();
 
 // Largest GEMM-order temporary of the integral-block build (2 GiB of doubles).
 constexpr int64_t kSlabDoubles = int64_t(1) << 28;
+// Default memory limit of the plan: MI355X HBM (288 GiB) less room for the runtime.
+constexpr size_t kDefaultMemLimit = size_t(270) << 30;
+// Rows of packed same-spin pairs per block of the Z-term expansion.
+constexpr int64_t kPairRowDoubles = int64_t(1) << 28;
+
+// Block sizes of one residual evaluation (see "Memory" above).
+struct Plan {
+  bool resident = true;   // (ae|bf), (me|bf) and their same-spin pair forms built once at init
+  int64_t es = 0;         // else rebuilt per residual in slabs of es virtual indices e
+  int64_t cj = 0;         // occupied columns j per block of the ring intermediates
+  int64_t ci = 0;         // occupied rows per block of expanded same-spin amplitudes
+};
 
 struct Context {
   rteom_options opt{};
@@ -52,26 +72,32 @@ struct Context {
   bool ws_owned = false;
   std::string err;
   bool failed = false;
+  Plan plan;
 
   int n = 0, nq = 0, na = 0, nb = 0, core_orb = 0, core_spin = 0;
   int no = 0, nv = 0, nx = 0;
   std::vector<int> O, V;
   std::vector<double> mo_h[2], mv_h[2];
   AmpLayout lay;
+  // fractions of existing spin-orbitals per extended index range (flop accounting)
+  double f_o[2] = {1, 1}, f_v[2] = {1, 1}, f_po[2] = {1, 1}, f_pv[2] = {1, 1};
 
   double* mo[2] = {nullptr, nullptr};
   double* mv[2] = {nullptr, nullptr};
   double* fo[2] = {nullptr, nullptr};
   double* fv[2] = {nullptr, nullptr};
+  int32_t* ptab = nullptr;             // pair tables: occupied (i, j), virtual (a, b)
   double *Loo = nullptr, *Lov = nullptr, *Lvv = nullptr, *Lvo = nullptr;
   double* f[2] = {nullptr, nullptr};   // undressed Fock of Phi, [nx][nx]
   double* h[2] = {nullptr, nullptr};   // one-body part h = f - G, [nx][nx]
   double* Jov = nullptr;               // (me|nf) as [m][e][n][f]
-  double* Vlad = nullptr;              // (ae|bf) as [e][f][a][b]
-  double* B1 = nullptr;                // (me|bf) as [e][f][m][b]
-  // Same-spin blocks in antisymmetric pair storage (pairs e < f, a < b in
-  // lexicographic order): <ab||ef> = (ae|bf) - (af|be) as [ef][ab], and
-  // (me|bf) - (mf|be) as [ef][m][b]
+  double* Jx = nullptr;                // (mf|ne) as [n][f][m][e]: the ring intermediates' exchange operand
+  double* Jp = nullptr;                // (me|nf) - (mf|ne) as [e<f][m<n]
+  // Resident plan only: (ae|bf) as [e][f][a][b], (me|bf) as [e][f][m][b], and the
+  // same-spin pair forms <ab||ef> = (ae|bf) - (af|be) as [e<f][a<b] and
+  // (me|bf) - (mf|be) as [e<f][m][b]
+  double* Vlad = nullptr;
+  double* B1 = nullptr;
   double* Wpp = nullptr;
   double* B1p = nullptr;
   // reduced precisions: the contractions' converted copies of those constant blocks
@@ -98,43 +124,91 @@ struct Context {
   int64_t nsteps = 0;
   std::vector<double> times;
   double eps_core = 0.0;               // N-electron orbital energy of the ionised orbital
-  double res_flops = 0.0;
-  double res_phase_flops[kNumPhases] = {0};
+  double res_flops = 0.0, res_alg_flops = 0.0;
+  double res_phase_flops[kNumPhases] = {0}, res_alg_phase_flops[kNumPhases] = {0};
 
   // ---------------------------------------------------------------- views
+  int64_t npo() const { return lay.npo(); }
+  int64_t npv() const { return lay.npv(); }
   View Lv(double* p, int64_t a, int64_t b) const { return make_view(p, nullptr, {nq, a, b}); }
   View t1(double* set, int s) const {
-    return make_view(set + s * lay.n1(), set + lay.size() + s * lay.n1(), {no, nv});
+    return with_frac(make_view(set + s * lay.n1(), set + lay.size() + s * lay.n1(), {no, nv}), {f_o[s], f_v[s]});
   }
-  View t2(double* set, int b) const {
-    double* p = set + 2 * lay.n1() + b * lay.n2();
-    return make_view(p, p + lay.size(), {no, no, nv, nv});
+  // alpha-beta doubles t_{i alpha, j beta}^{a alpha, b beta} as [i][j][a][b]
+  View tab(double* set) const {
+    double* p = set + lay.off_ab();
+    return with_frac(make_view(p, p + lay.size(), {no, no, nv, nv}), {f_o[0], f_o[1], f_v[0], f_v[1]});
   }
-  // spin-aligned doubles block t_{i s, m u}^{a s, e u} as a [i][m][a][e] view
-  View TT(double* set, int s, int u) const {
-    if (s == u) return t2(set, s == 0 ? 0 : 2);
-    View ab = t2(set, 1);
-    return s == 0 ? ab : reorder(ab, {1, 0, 3, 2});
+  // the same rows as [(i,j)][e][f]
+  View tab3(double* set) const {
+    double* p = set + lay.off_ab();
+    return with_frac(make_view(p, p + lay.size(), {(int64_t)no * no, nv, nv}), {f_o[0] * f_o[1], f_v[0], f_v[1]});
+  }
+  // t_{i s, m u}^{a s, e u} for s != u as [i][m][a][e]
+  View tsu(double* set, int s) const { return s == 0 ? tab(set) : reorder(tab(set), {1, 0, 3, 2}); }
+  // same-spin block s in pair storage [i<j][a<b]
+  View tss(double* set, int s) const {
+    double* p = set + lay.off_ss(s);
+    return with_frac(make_view(p, p + lay.size(), {npo(), npv()}), {f_po[s], f_pv[s]});
+  }
+  // both same-spin blocks as one [(s, i<j)][a<b]
+  View tss2(double* set) const {
+    double* p = set + lay.off_ss(0);
+    return with_frac(make_view(p, p + lay.size(), {2 * npo(), npv()}),
+                     {0.5 * (f_po[0] + f_po[1]), 0.5 * (f_pv[0] + f_pv[1])});
   }
   View fview(double* p, int64_t r0, int64_t c0, int64_t nr, int64_t nc, bool cplx) const {
     View v = make_view(p, cplx ? p + (int64_t)nx * nx : nullptr, {nx, nx});
     return block(v, {r0, c0}, {nr, nc});
   }
   View vec(double* p, int64_t n) const { return make_view(p, nullptr, {n}); }
-  static int64_t npairs(int64_t n) { return n * (n - 1) / 2; }
-  // the two same-spin doubles blocks (0: alpha alpha, 2: beta beta) of a set and
-  // a packed [2][pairs (i<j)][...] array
-  PairOp same_spin_pairs(double* set_blocks, const View& packed, int64_t n2, int pair2) const {
-    PairOp op;
-    op.n1 = no; op.n2 = n2; op.nblk = 2; op.pair2 = pair2;
-    op.x_re = set_blocks; op.x_im = set_blocks + lay.size(); op.x_bs = 2 * lay.n2();
-    op.y_re = packed.re; op.y_im = packed.im; op.y_bs = packed.numel() / 2;
+  PairTables tables() const {
+    PairTables t;
+    t.oi = ptab;
+    t.oj = ptab + npo();
+    t.va = ptab + 2 * npo();
+    t.vb = ptab + 2 * npo() + npv();
+    return t;
+  }
+  SsOp ss_op(int mode, double* set, int s) const {
+    SsOp op;
+    op.mode = mode;
+    op.n1 = no;
+    op.n2 = nv;
+    op.y_re = set + lay.off_ss(s);
+    op.y_im = set + lay.size() + lay.off_ss(s);
+    op.pt = tables();
     return op;
+  }
+  // Rows i0 .. i0+ci-1 (all j) of same-spin block s, expanded to full storage [ci][no][nv][nv].
+  View expand_rows(double* set, int s, int64_t i0, int64_t ci) {
+    View x = eng.temp({ci, no, nv, nv}, true);
+    SsOp op = ss_op(SsOp::kExpand, set, s);
+    op.i0 = i0; op.ci = ci; op.j0 = 0; op.cj = no;
+    op.x_re = x.re; op.x_im = x.im;
+    eng.ss(op);
+    return with_frac(x, {f_o[s], f_o[s], f_v[s], f_v[s]});
+  }
+  // Same-spin block s of set += alpha * (antisymmetric part of) the block x of rows i0..,
+  // columns j0.. (SsOp::kAccum).
+  void accum(double* set, int s, const View& x, int64_t i0, int64_t j0, double alpha, int anti1, int anti2) {
+    SsOp op = ss_op(SsOp::kAccum, set, s);
+    op.i0 = i0; op.ci = x.dim[0]; op.j0 = j0; op.cj = x.dim[1];
+    op.x_re = x.re; op.x_im = x.im;
+    op.alpha = alpha; op.anti1 = anti1; op.anti2 = anti2;
+    eng.ss(op);
+  }
+  View sstemp(std::initializer_list<int64_t> dims, int s) {
+    View x = eng.temp(dims, true);
+    return with_frac(x, {f_o[s], f_o[s], f_v[s], f_v[s]});
   }
 
   double* take(int64_t n) { return arena.take(n); }
   void h2d(double* dst, const double* src, int64_t n) {
     if (!dry) be->h2d(dst, src, n * sizeof(double));
+  }
+  void fill(double* p, int64_t n) {
+    if (!dry) be->fill(p, n, 0.0);
   }
   void check() {
     if (dry) return;
@@ -167,11 +241,53 @@ struct Context {
     for (int s = 0; s < 2; ++s) {
       mo_h[s].resize(no);
       mv_h[s].resize(nv);
-      for (int i = 0; i < no; ++i) mo_h[s][i] = occ[s][O[i]];
-      for (int a = 0; a < nv; ++a) mv_h[s][a] = vir[s][V[a]];
+      int cnt_o = 0, cnt_v = 0;
+      for (int i = 0; i < no; ++i) cnt_o += (mo_h[s][i] = occ[s][O[i]]) != 0;
+      for (int a = 0; a < nv; ++a) cnt_v += (mv_h[s][a] = vir[s][V[a]]) != 0;
+      f_o[s] = no ? (double)cnt_o / no : 1.0;
+      f_v[s] = nv ? (double)cnt_v / nv : 1.0;
+      f_po[s] = npairs(no) ? (double)npairs(cnt_o) / npairs(no) : 1.0;
+      f_pv[s] = npairs(nv) ? (double)npairs(cnt_v) / npairs(nv) : 1.0;
     }
     lay.no = no;
     lay.nv = nv;
+  }
+
+  // (ae|bf) [ce][nv][nv][nv], <ab||ef> rows [pairs (e<f), e in slab][a<b], (me|bf)
+  // [ce][nv][no][nv] and (me|bf) - (mf|be) rows [pairs (e<f), e in slab][m][b] for the
+  // virtual indices e0 .. e0+ce-1 (Sec. 2.3: (pq|rs) = sum_Q L^Q_pq L^Q_rs), in the
+  // engine's current precision.
+  void build_slab(int64_t e0, int64_t ce, const View& Vs, double* Wdst, const View& Bs, double* Bpdst) {
+    const int64_t Q = nq;
+    {
+      // the product lands in a GEMM-order temporary before it is permuted into
+      // place: sub-slabs of e bound that temporary to kSlabDoubles
+      const int64_t per_e = std::max<int64_t>(1, (int64_t)nv * nv * nv);
+      const int64_t sub = std::max<int64_t>(1, std::min<int64_t>(ce, kSlabDoubles / per_e));
+      for (int64_t k = 0; k < ce; k += sub) {
+        const int64_t m = std::min<int64_t>(sub, ce - k);
+        View Le = block(Lv(Lvv, nv, nv), {0, 0, e0 + k}, {Q, nv, m});
+        View Lm = block(Lv(Lov, no, nv), {0, 0, e0 + k}, {Q, no, m});
+        eng.contract("Qae,Qbf->efab", Le, Lv(Lvv, nv, nv), block(Vs, {k, 0, 0, 0}, {m, nv, nv, nv}), 1.0, 0);
+        eng.contract("Qme,Qbf->efmb", Lm, Lv(Lvv, nv, nv), block(Bs, {k, 0, 0, 0}, {m, nv, no, nv}), 1.0, 0);
+      }
+    }
+    SsOp w;
+    w.mode = SsOp::kPackSlab;
+    w.n1 = nv; w.n2 = nv; w.pair2 = 1; w.i0 = e0; w.ci = ce;
+    w.x_re = Vs.re; w.y_re = Wdst;
+    eng.ss(w);
+    const size_t mk = arena.mark();
+    View Xs = eng.temp({ce, nv, no, nv}, false);
+    eng.add(Xs, Bs, 1.0, 0.0, 0);
+    // (mf|be) for e in the slab: sum_Q L^Q_mf L^Q_be
+    eng.contract("Qmf,Qbe->efmb", Lv(Lov, no, nv), block(Lv(Lvv, nv, nv), {0, 0, e0}, {Q, nv, ce}), Xs, -1.0, 1);
+    SsOp z;
+    z.mode = SsOp::kPackSlab;
+    z.n1 = nv; z.n2 = (int64_t)no * nv; z.pair2 = 0; z.i0 = e0; z.ci = ce;
+    z.x_re = Xs.re; z.y_re = Bpdst;
+    eng.ss(z);
+    arena.release(mk);
   }
 
   void init(const double* eps, const double* chol) {
@@ -194,24 +310,42 @@ struct Context {
       f[s] = take((int64_t)nx * nx);
       h[s] = take((int64_t)nx * nx);
     }
+    {
+      const int64_t nt = 2 * npo() + 2 * npv();
+      ptab = reinterpret_cast<int32_t*>(take((nt + 1) / 2));
+      if (!dry) {
+        std::vector<int32_t> t(nt);
+        int64_t k = 0;
+        for (int i = 0; i < no; ++i)
+          for (int j = i + 1; j < no; ++j) { t[k] = i; t[npo() + k] = j; ++k; }
+        k = 0;
+        for (int a = 0; a < nv; ++a)
+          for (int b = a + 1; b < nv; ++b) { t[2 * npo() + k] = a; t[2 * npo() + npv() + k] = b; ++k; }
+        be->h2d(ptab, t.data(), nt * sizeof(int32_t));
+      }
+    }
     Loo = take(Q * no * no);
     Lov = take(Q * no * nv);
     Lvv = take(Q * nv * nv);
     Lvo = take(Q * nv * no);
     Jov = take((int64_t)no * nv * no * nv);
-    Vlad = take((int64_t)nv * nv * nv * nv);
-    B1 = take((int64_t)nv * nv * no * nv);
-    Wpp = take(npairs(nv) * npairs(nv));
-    B1p = take(npairs(nv) * no * nv);
-    if (opt.prec != RTEOM_FP64) {
-      const int64_t v2 = (int64_t)nv * nv, pv = npairs(nv), ov = (int64_t)no * nv;
-      const std::pair<ConvSlot*, int64_t> slots[4] = {
-          {&conv_v, conv_doubles(v2, v2)}, {&conv_w, conv_doubles(pv, pv)},
-          {&conv_b1, conv_doubles(ov, v2)}, {&conv_b1p, conv_doubles(ov, pv)}};
-      for (const auto& sl : slots) {
-        *sl.first = ConvSlot();
-        sl.first->doubles = sl.second;
-        sl.first->p = take(sl.second);
+    Jx = take((int64_t)no * nv * no * nv);
+    Jp = take(npv() * npo());
+    if (plan.resident) {
+      Vlad = take((int64_t)nv * nv * nv * nv);
+      B1 = take((int64_t)nv * nv * no * nv);
+      Wpp = take(npv() * npv());
+      B1p = take(npv() * no * nv);
+      if (opt.prec != RTEOM_FP64) {
+        const int64_t v2 = (int64_t)nv * nv, pv = npv(), ov = (int64_t)no * nv;
+        const std::pair<ConvSlot*, int64_t> slots[4] = {
+            {&conv_v, conv_doubles(v2, v2)}, {&conv_w, conv_doubles(pv, pv)},
+            {&conv_b1, conv_doubles(ov, v2)}, {&conv_b1p, conv_doubles(ov, pv)}};
+        for (const auto& sl : slots) {
+          *sl.first = ConvSlot();
+          sl.first->doubles = sl.second;
+          sl.first->p = take(sl.second);
+        }
       }
     }
     const int64_t ns = lay.size();
@@ -318,34 +452,33 @@ struct Context {
       eng.add(vec(fv[s], nv), Fv, 1.0, 0.0, 0);
     }
     arena.release(mk);
-    // Resident integral blocks (spin free)
+    // Resident integral blocks (spin free): (me|nf) and its pair form over (e<f), (m<n)
     eng.contract("Qme,Qnf->menf", Lv(Lov, no, nv), Lv(Lov, no, nv),
                  make_view(Jov, nullptr, {no, nv, no, nv}), 1.0, 0);
-    // (ae|bf) and (me|bf) are built in slabs of e: the product lands in a temporary
-    // in GEMM order before it is permuted into place, and a slab bounds that
-    // temporary to kSlabDoubles instead of a second copy of the whole block.
+    // Jx[n][f][m][e] = (mf|ne) = Jov[m][f][n][e]
+    eng.add(make_view(Jx, nullptr, {no, nv, no, nv}),
+            reorder(make_view(Jov, nullptr, {no, nv, no, nv}), {2, 1, 0, 3}), 1.0, 0.0, 0);
     {
-      const int64_t per_e = std::max<int64_t>(1, (int64_t)nv * nv * nv);
-      const int64_t ce = std::max<int64_t>(1, std::min<int64_t>(nv, kSlabDoubles / per_e));
+      const size_t mj = arena.mark();
+      View t = eng.temp({nv, nv, no, no}, false);
+      eng.add(t, reorder(make_view(Jov, nullptr, {no, nv, no, nv}), {1, 3, 0, 2}), 1.0, 0.0, 0);
+      SsOp p;
+      p.mode = SsOp::kPackSlab;
+      p.n1 = nv; p.n2 = no; p.pair2 = 1; p.i0 = 0; p.ci = nv;
+      p.x_re = t.re; p.y_re = Jp;
+      eng.ss(p);   // Jp[e<f][m<n] = (me|nf) - (ne|mf)
+      arena.release(mj);
+    }
+    if (plan.resident) {
+      // built in slabs of e (GEMM-order temporaries bounded by kSlabDoubles)
       View Vv = make_view(Vlad, nullptr, {nv, nv, nv, nv});
       View Bv = make_view(B1, nullptr, {nv, nv, no, nv});
+      const int64_t ce = std::max<int64_t>(1, std::min<int64_t>(nv, kSlabDoubles / std::max<int64_t>(1, (int64_t)nv * nv * nv)));
       for (int64_t e0 = 0; e0 < nv; e0 += ce) {
-        const int64_t n = std::min<int64_t>(ce, nv - e0);
-        View Le = block(Lv(Lvv, nv, nv), {0, 0, e0}, {Q, nv, n});
-        View Lm = block(Lv(Lov, no, nv), {0, 0, e0}, {Q, no, n});
-        eng.contract("Qae,Qbf->efab", Le, Lv(Lvv, nv, nv), block(Vv, {e0, 0, 0, 0}, {n, nv, nv, nv}), 1.0, 0);
-        eng.contract("Qme,Qbf->efmb", Lm, Lv(Lvv, nv, nv), block(Bv, {e0, 0, 0, 0}, {n, nv, no, nv}), 1.0, 0);
+        const int64_t m = std::min<int64_t>(ce, nv - e0);
+        build_slab(e0, m, block(Vv, {e0, 0, 0, 0}, {m, nv, nv, nv}), Wpp + pair_start(e0, nv) * npv(),
+                   block(Bv, {e0, 0, 0, 0}, {m, nv, no, nv}), B1p + pair_start(e0, nv) * no * nv);
       }
-    }
-    {
-      PairOp w;
-      w.n1 = nv; w.n2 = nv; w.pair2 = 1; w.anti = 1;
-      w.x_re = Vlad; w.y_re = Wpp;
-      eng.pairs(w);
-      PairOp z;
-      z.n1 = nv; z.n2 = (int64_t)no * nv; z.pair2 = 0; z.anti = 1;
-      z.x_re = B1; z.y_re = B1p;
-      eng.pairs(z);
     }
     // T(0) = 0, C(0) = 0
     if (!dry) {
@@ -361,37 +494,94 @@ struct Context {
   }
 
   // --------------------------------------------------------- residual
+  // Integral products of the virtual slab e0 .. e0+ce-1: the particle-particle ladder
+  // (alpha-beta in full storage, same-spin over pairs) and the Z intermediates.
+  void slab_products(double* Xs, double* Rs, int64_t e0, int64_t ce, const View& Vs, double* Wsl, const View& Bs,
+                     double* Bpsl, const View& Z3ab, const View& Zp, const View& Z2ab, bool first) {
+    const int64_t r0 = pair_start(e0, nv), nr = pair_start(e0 + ce, nv) - r0;
+    const int64_t nov = (int64_t)no * nv;
+    const bool res = plan.resident;
+    View Tab = block(tab3(Xs), {0, e0, 0}, {(int64_t)no * no, ce, nv});
+    View Tp = block(tss2(Xs), {0, r0}, {2 * npo(), nr});
+    eng.set_phase(kPhaseLadder);
+    eng.contract("Pef,efab->Pab", Tab, Vs, tab3(Rs), 1.0, 1, res ? &conv_v : nullptr);
+    if (nr > 0)
+      eng.contract("Pr,rq->Pq", Tp, make_view(Wsl, nullptr, {nr, npv()}), tss2(Rs), 1.0, 1, res ? &conv_w : nullptr);
+    eng.set_phase(kPhaseRing);
+    // Z_ij,mb = sum_ef T_ijef (me|bf); same-spin: sum_{e<f} T_ijef [(me|bf) - (mf|be)]
+    eng.contract("Pef,efmb->Pmb", Tab, Bs, Z3ab, 1.0, first ? 0 : 1, res ? &conv_b1 : nullptr);
+    if (nr > 0)
+      eng.contract("Pr,rc->Pc", Tp, make_view(Bpsl, nullptr, {nr, nov}), Zp, 1.0, first ? 0 : 1,
+                   res ? &conv_b1p : nullptr);
+    else if (first)
+      eng.add(Zp, Zp, 0.0, 0.0, 0);
+    // Z2_ij,an = sum_ef T_ijef (ae|nf), here over f in the slab: (me|bf) as [f][e][n][a]
+    eng.contract("ijef,fena->ijan", block(tab(Xs), {0, 0, 0, e0}, {no, no, nv, ce}), Bs, Z2ab, 1.0, first ? 0 : 1);
+    eng.set_phase(kPhaseGemm);
+  }
+
+  // Zero the amplitudes of spin-orbitals that do not exist.
+  void mask_set(double* set) {
+    for (int s = 0; s < 2; ++s) {
+      const double* sc[2] = {mo[s], mv[s]};
+      eng.scale(t1(set, s), sc);
+      SsOp m = ss_op(SsOp::kMask, set, s);
+      m.m1 = mo[s];
+      m.m2 = mv[s];
+      eng.ss(m);
+    }
+    const double* sc[4] = {mo[0], mo[1], mv[0], mv[1]};
+    eng.scale(tab(set), sc);
+  }
+
   // R <- <Phi_x| e^{-T} H_N e^{T} |Phi> for T = Xs (all five blocks, masked).
   void residual(double* Xs, double* Rs) {
     const int64_t Q = nq;
     const size_t mk = arena.mark();
     eng.prec = opt.prec;     // the residual's contractions in the requested precision
-    eng.flops = 0.0;
-    for (double& f : eng.phase_flops) f = 0.0;
+    eng.flops = eng.alg_flops = 0.0;
+    for (int k = 0; k < kNumPhases; ++k) eng.phase_flops[k] = eng.alg_phase_flops[k] = 0.0;
     eng.set_phase(kPhaseGemm);
+    fill(Rs, 2 * lay.size());        // every term below accumulates
+    const int64_t nov = (int64_t)no * nv;
+    const int64_t ci = std::max<int64_t>(1, std::min<int64_t>(plan.ci, no));
+    const int64_t cj = std::max<int64_t>(1, std::min<int64_t>(plan.cj, no));
     View Lov_v = Lv(Lov, no, nv);
-    View Ldoo[2], Ldvv[2], Ldvo[2], fd[2], D[2], Lbar[2], Fvv[2], Foo[2];
+    View Jv = make_view(Jov, nullptr, {no, nv, no, nv});
+    View Jxv = make_view(Jx, nullptr, {no, nv, no, nv});
+    // intermediates that live through the whole evaluation
+    View Ldoo[2], Ldvo[2], fd[2], D[2], Lbar[2], Fvv[2], Foo[2];
+    for (int s = 0; s < 2; ++s) {
+      Ldoo[s] = with_frac(eng.temp({Q, no, no}, true), {1, f_o[s], f_o[s]});
+      Ldvo[s] = with_frac(eng.temp({Q, nv, no}, true), {1, f_v[s], f_o[s]});
+      fd[s] = eng.temp({nx, nx}, true);
+      D[s] = with_frac(eng.temp({Q, no, nv}, true), {1, f_o[s], f_v[s]});
+      Lbar[s] = with_frac(eng.temp({Q, nv, no}, true), {1, f_v[s], f_o[s]});
+      Fvv[s] = with_frac(eng.temp({nv, nv}, true), {f_v[s], f_v[s]});
+      Foo[s] = with_frac(eng.temp({no, no}, true), {f_o[s], f_o[s]});
+    }
+    View jq = eng.temp({Q}, true);
+    // the dressed virtual-virtual vectors are needed up to the ring intermediates only
+    const size_t mk_vv = arena.mark();
+    View Ldvv[2];
+    for (int s = 0; s < 2; ++s) Ldvv[s] = with_frac(eng.temp({Q, nv, nv}, true), {1, f_v[s], f_v[s]});
     // dressed Cholesky vectors L~ = (1 - t) L (1 + t)
     for (int s = 0; s < 2; ++s) {
       View t = t1(Xs, s);
-      Ldoo[s] = eng.temp({Q, no, no}, true);
       eng.add(Ldoo[s], Lv(Loo, no, no), 1, 0, 0);
       eng.contract("Qmf,if->Qmi", Lov_v, t, Ldoo[s], 1.0, 1);
-      Ldvv[s] = eng.temp({Q, nv, nv}, true);
       eng.add(Ldvv[s], Lv(Lvv, nv, nv), 1, 0, 0);
       eng.contract("ma,Qme->Qae", t, Lov_v, Ldvv[s], -1.0, 1);
-      Ldvo[s] = eng.temp({Q, nv, no}, true);
       eng.add(Ldvo[s], Lv(Lvo, nv, no), 1, 0, 0);
       eng.contract("Qaf,if->Qai", Lv(Lvv, nv, nv), t, Ldvo[s], 1.0, 1);
       eng.contract("ma,Qmi->Qai", t, Ldoo[s], Ldvo[s], -1.0, 1);
     }
     // dressed Fock of Phi: f~ = (1 - t) h (1 + t) + J~ - K~
-    View jq = eng.temp({Q}, true);
     for (int t = 0; t < 2; ++t)
       eng.contract("Qk,k->Q", diagonal(Ldoo[t], 1, 2), vec(mo[t], no), jq, 1.0, t);
     for (int s = 0; s < 2; ++s) {
+      const size_t mf = arena.mark();
       View t = t1(Xs, s);
-      fd[s] = eng.temp({nx, nx}, true);
       double* base = fd[s].re;
       View foo = fview(base, 0, 0, no, no, true), fov = fview(base, 0, no, no, nv, true);
       View fvo = fview(base, no, 0, nv, no, true), fvv = fview(base, no, no, nv, nv, true);
@@ -418,184 +608,220 @@ struct Context {
       eng.contract("Qmk,Qke->me", Loo_m, Lov_v, fov, -1.0, 1);
       eng.contract("Qak,Qke->ae", Lvo_m, Lov_v, fvv, -1.0, 1);
       eng.contract("Qak,Qki->ai", Lvo_m, Ldoo[s], fvo, -1.0, 1);
+      arena.release(mf);
     }
-    // D^Q_ia = sum_{me} T_imae L^Q_me summed over the spin of (m, e)
-    for (int s = 0; s < 2; ++s) {
-      D[s] = eng.temp({Q, no, nv}, true);
-      eng.contract("imae,Qme->Qia", TT(Xs, s, s), Lov_v, D[s], 1.0, 0);
-      eng.contract("imae,Qme->Qia", TT(Xs, s, 1 - s), Lov_v, D[s], 1.0, 1);
-      Lbar[s] = eng.temp({Q, nv, no}, true);
-      eng.add(Lbar[s], Ldvo[s], 1, 0, 0);
-      eng.add(Lbar[s], reorder(D[s], {0, 2, 1}), 1, 0, 1);
-      Fvv[s] = eng.temp({nv, nv}, true);
-      eng.add(Fvv[s], fview(fd[s].re, no, no, nv, nv, true), 1, 0, 0);
-      eng.contract("Qmb,Qme->be", D[s], Lov_v, Fvv[s], -1.0, 1);
-      Foo[s] = eng.temp({no, no}, true);
-      eng.add(Foo[s], fview(fd[s].re, 0, 0, no, no, true), 1, 0, 0);
-      eng.contract("Qme,Qje->mj", Lov_v, D[s], Foo[s], 1.0, 1);
-    }
-    // singles
+    // D^Q_ia = sum_{me} T_imae L^Q_me summed over the spin of (m, e), and the singles'
+    // T2 terms, over blocks of rows i of the expanded same-spin amplitudes
     for (int s = 0; s < 2; ++s) {
       const int u = 1 - s;
       View r1 = t1(Rs, s);
-      eng.add(r1, reorder(fview(fd[s].re, no, 0, nv, no, true), {1, 0}), 1, 0, 0);
-      eng.contract("me,imae->ia", fview(fd[s].re, 0, no, no, nv, true), TT(Xs, s, s), r1, 1.0, 1);
-      eng.contract("me,imae->ia", fview(fd[u].re, 0, no, no, nv, true), TT(Xs, s, u), r1, 1.0, 1);
+      eng.contract("imae,Qme->Qia", tsu(Xs, s), Lov_v, D[s], 1.0, 0);
+      eng.contract("me,imae->ia", fview(fd[u].re, 0, no, no, nv, true), tsu(Xs, s), r1, 1.0, 1);
+      for (int64_t i0 = 0; i0 < no; i0 += ci) {
+        const int64_t m = std::min<int64_t>(ci, no - i0);
+        const size_t mr = arena.mark();
+        View xt = expand_rows(Xs, s, i0, m);
+        eng.contract("imae,Qme->Qia", xt, Lov_v, block(D[s], {0, i0, 0}, {Q, m, nv}), 1.0, 1);
+        eng.contract("me,imae->ia", fview(fd[s].re, 0, no, no, nv, true), xt, block(r1, {i0, 0}, {m, nv}), 1.0, 1);
+        arena.release(mr);
+      }
+      eng.add(Lbar[s], Ldvo[s], 1, 0, 0);
+      eng.add(Lbar[s], reorder(D[s], {0, 2, 1}), 1, 0, 1);
+      eng.add(Fvv[s], fview(fd[s].re, no, no, nv, nv, true), 1, 0, 0);
+      eng.contract("Qmb,Qme->be", D[s], Lov_v, Fvv[s], -1.0, 1);
+      eng.add(Foo[s], fview(fd[s].re, 0, 0, no, no, true), 1, 0, 0);
+      eng.contract("Qme,Qje->mj", Lov_v, D[s], Foo[s], 1.0, 1);
+      // remaining singles terms
+      eng.add(r1, reorder(fview(fd[s].re, no, 0, nv, no, true), {1, 0}), 1, 0, 1);
       eng.contract("Qae,Qie->ia", Ldvv[s], D[s], r1, 1.0, 1);
       eng.contract("Qmi,Qma->ia", Ldoo[s], D[s], r1, -1.0, 1);
-      const double* sc[2] = {mo[s], mv[s]};
-      eng.scale(r1, sc);
     }
-    // ring intermediates W[(m,e),(b,j)]: exchange blocks WX(s,u) (m,j in s; b,e in u)
-    // and the opposite-spin exchange blocks V(s->u) (m,e in s; j,b in u)
-    View Jv = make_view(Jov, nullptr, {no, nv, no, nv});
-    View WX[2][2], Vx[2];
+    // Ring terms P(ij) P(ab) sum_me t_imae W_mbej through the intermediates
+    // W[(m,e),(b,j)], built and used for a block of j at a time: exchange blocks
+    // WX(s,u) (m, j in s; b, e in u) and the opposite-spin blocks V(s) (m, e in s;
+    // j, b in u).
     eng.set_phase(kPhaseRing);
-    for (int s = 0; s < 2; ++s)
-      for (int u = 0; u < 2; ++u) {
-        WX[s][u] = eng.temp({no, nv, nv, no}, true);
-        eng.contract("Qmj,Qbe->mbej", Ldoo[s], Ldvv[u], WX[s][u], -1.0, 0);
-        eng.contract("jnfb,mfne->mbej", TT(Xs, s, u), Jv, WX[s][u], 0.5, 1);
+    for (int64_t j0 = 0; j0 < no; j0 += cj) {
+      const int64_t n = std::min<int64_t>(cj, no - j0);
+      const size_t mw = arena.mark();
+      View WX[2][2], Vx[2];
+      for (int s = 0; s < 2; ++s)
+        for (int u = 0; u < 2; ++u) {
+          WX[s][u] = with_frac(eng.temp({no, nv, nv, n}, true), {f_o[s], f_v[u], f_v[u], f_o[s]});
+          eng.contract("Qmj,Qbe->mbej", block(Ldoo[s], {0, 0, j0}, {Q, no, n}), Ldvv[u], WX[s][u], -1.0, 0);
+          const size_t mr = arena.mark();
+          View tj = s == u ? expand_rows(Xs, s, j0, n) : block(tsu(Xs, s), {j0, 0, 0, 0}, {n, no, nv, nv});
+          eng.contract("jnfb,nfme->mbej", tj, Jxv, WX[s][u], 0.5, 1);
+          arena.release(mr);
+        }
+      for (int s = 0; s < 2; ++s) {
+        const int u = 1 - s;
+        Vx[s] = with_frac(eng.temp({no, nv, nv, n}, true), {f_o[s], f_v[u], f_v[s], f_o[u]});
+        eng.contract("jnbf,nfme->mbej", block(tsu(Xs, u), {j0, 0, 0, 0}, {n, no, nv, nv}), Jxv, Vx[s], -0.5, 0);
       }
-    for (int s = 0; s < 2; ++s) {
-      const int u = 1 - s;
-      Vx[s] = eng.temp({no, nv, nv, no}, true);
-      eng.contract("jnbf,mfne->mbej", TT(Xs, u, s), Jv, Vx[s], -0.5, 0);
+      // same-spin residuals: x[i][j] over blocks of rows i, antisymmetrised into pairs
+      for (int s = 0; s < 2; ++s) {
+        const int u = 1 - s;
+        for (int64_t i0 = 0; i0 < no; i0 += ci) {
+          const int64_t m = std::min<int64_t>(ci, no - i0);
+          const size_t mr = arena.mark();
+          View x = sstemp({m, n, nv, nv}, s);
+          View xt = expand_rows(Xs, s, i0, m);
+          eng.contract("imae,mbej->ijab", xt, WX[s][s], x, 1.0, 0);
+          eng.contract("imae,mbej->ijab", block(tsu(Xs, s), {i0, 0, 0, 0}, {m, no, nv, nv}), Vx[u], x, 1.0, 1);
+          accum(Rs, s, x, i0, j0, 1.0, 1, 1);
+          arena.release(mr);
+        }
+      }
+      // alpha-beta residual (full storage): blocks of the residual's first two indices,
+      // one of them the intermediate's last index j (the W block), the other a block of
+      // the amplitudes' free occupied index
+      View Rab = tab(Rs), Tab = tab(Xs);
+      for (int64_t i0 = 0; i0 < no; i0 += ci) {
+        const int64_t m = std::min<int64_t>(ci, no - i0);
+        View Ti = block(Tab, {i0, 0, 0, 0}, {m, no, nv, nv});   // rows i of t_{i alpha, m beta}
+        View Tj = block(Tab, {0, i0, 0, 0}, {no, m, nv, nv});   // columns j of t_{m alpha, j beta}
+        View Rij = block(Rab, {i0, j0, 0, 0}, {m, n, nv, nv});  // i in the amplitude block, j in W's
+        View Rji = block(Rab, {j0, i0, 0, 0}, {n, m, nv, nv});  // i in W's block, j in the amplitude block
+        eng.contract("imae,mbej->ijab", Ti, WX[1][1], Rij, 1.0, 1);
+        eng.contract("mjae,mbei->ijab", Tj, WX[0][1], Rji, 1.0, 1);
+        eng.contract("imeb,maej->ijab", Ti, WX[1][0], Rij, 1.0, 1);
+        eng.contract("mjeb,maei->ijab", Tj, WX[0][0], Rji, 1.0, 1);
+        const size_t mr = arena.mark();
+        View xa = expand_rows(Xs, 0, i0, m);
+        eng.contract("imae,mbej->ijab", xa, Vx[0], Rij, 1.0, 1);
+        arena.release(mr);
+        View xb = expand_rows(Xs, 1, i0, m);
+        eng.contract("jmbe,maei->ijab", xb, Vx[1], Rji, 1.0, 1);
+        arena.release(mr);
+      }
+      arena.release(mw);
     }
     eng.set_phase(kPhaseGemm);
-    View x = eng.temp({no, no, nv, nv}, true);
-    View tau = eng.temp({no, no, nv, nv}, true);
-    View g = eng.temp({no, no, no, no}, true);
-    View gA = eng.temp({no, no, no, no}, true);
-    View Xo = eng.temp({no, no, no, no}, true);
-    View Vl = make_view(Vlad, nullptr, {nv, nv, nv, nv});
-    View Bv = make_view(B1, nullptr, {nv, nv, no, nv});
-    // all three doubles blocks are contiguous: [3 * no * no][nv][nv]
-    const int64_t P3 = 3 * (int64_t)no * no;
-    double* x2 = Xs + 2 * lay.n1();
-    double* r2 = Rs + 2 * lay.n1();
-    // same-spin doubles in pair storage [2][i<j][e<f] (T is antisymmetric in both pairs)
-    const int64_t npo = npairs(no), npv = npairs(nv), nov = (int64_t)no * nv;
-    View Tp = eng.temp({2 * npo, npv}, true);
-    eng.pairs(same_spin_pairs(x2, Tp, nv, 1));
-    View Tab = make_view(x2 + lay.n2(), x2 + lay.size() + lay.n2(), {(int64_t)no * no, nv, nv});
-    View Rab = make_view(r2 + lay.n2(), r2 + lay.size() + lay.n2(), {(int64_t)no * no, nv, nv});
-    // T1 part of the dressed virtual vectors ("Z" terms): Z_ij,mb = sum_ef T_ijef (me|bf),
-    // for the same-spin blocks sum_{e<f} T_ijef [(me|bf) - (mf|be)] over pairs i < j
-    View Z3 = eng.temp({P3, no, nv}, true);
-    eng.set_phase(kPhaseRing);
-    {
-      const int64_t zb = (int64_t)no * no * nov;
-      eng.contract("Pef,efmb->Pmb", Tab, Bv, make_view(Z3.re + zb, Z3.im + zb, {(int64_t)no * no, no, nv}), 1.0, 0,
-                   &conv_b1);
-      const size_t mz = arena.mark();
-      View Zp = eng.temp({2 * npo, nov}, true);
-      eng.contract("Pq,qc->Pc", Tp, make_view(B1p, nullptr, {npv, nov}), Zp, 1.0, 0, &conv_b1p);
-      PairOp u;
-      u.n1 = no; u.n2 = nov; u.nblk = 2; u.pair2 = 0; u.mode = 1; u.beta = 0;
-      u.x_re = Z3.re; u.x_im = Z3.im; u.x_bs = 2 * zb;
-      u.y_re = Zp.re; u.y_im = Zp.im; u.y_bs = npo * nov;
-      eng.pairs(u);
-      arena.release(mz);
+    arena.release(mk_vv);
+    // Z intermediates (from the integral slabs on)
+    View Z3ab = with_frac(eng.temp({(int64_t)no * no, no, nv}, true), {f_o[0] * f_o[1], f_o[0], f_v[1]});
+    View Zp = eng.temp({2 * npo(), nov}, true);
+    View Z2ab = with_frac(eng.temp({no, no, nv, no}, true), {f_o[0], f_o[1], f_v[0], f_o[1]});
+    // Particle-particle ladder and Z intermediates over virtual slabs of e: the resident
+    // blocks at once, or each slab rebuilt from the Cholesky vectors
+    if (plan.resident) {
+      slab_products(Xs, Rs, 0, nv, make_view(Vlad, nullptr, {nv, nv, nv, nv}), Wpp,
+                    make_view(B1, nullptr, {nv, nv, no, nv}), B1p, Z3ab, Zp, Z2ab, true);
+    } else {
+      const int64_t es = std::max<int64_t>(1, std::min<int64_t>(plan.es, nv));
+      for (int64_t e0 = 0; e0 < nv; e0 += es) {
+        const int64_t ce = std::min<int64_t>(es, nv - e0);
+        const int64_t nr = pair_start(e0 + ce, nv) - pair_start(e0, nv);
+        const size_t ms = arena.mark();
+        double* Wsl = take(std::max<int64_t>(1, nr * npv()));
+        double* Bpsl = take(std::max<int64_t>(1, nr * nov));
+        View Vs = eng.temp({ce, nv, nv, nv}, false);
+        View Bs = eng.temp({ce, nv, no, nv}, false);
+        eng.set_phase(kPhaseBuild);
+        build_slab(e0, ce, Vs, Wsl, Bs, Bpsl);
+        eng.set_phase(kPhaseGemm);
+        slab_products(Xs, Rs, e0, ce, Vs, Wsl, Bs, Bpsl, Z3ab, Zp, Z2ab, e0 == 0);
+        arena.release(ms);
+      }
     }
-    eng.set_phase(kPhaseGemm);
-    // same-spin doubles
+    // same-spin doubles: the terms in full storage over blocks of rows, the hole
+    // ladders and the Z term in pair storage
     for (int s = 0; s < 2; ++s) {
-      const int u = 1 - s;
-      const int blk = s == 0 ? 0 : 2;
-      View Rv = t2(Rs, blk), T = t2(Xs, blk), t = t1(Xs, s);
-      // dressed <ab||ij> plus Coulomb ring: Lbar_ai Lbar_bj - Lbar_aj Lbar_bi
-      eng.contract("Qai,Qbj->ijab", Lbar[s], Lbar[s], x, 1.0, 0);
-      eng.add(Rv, x, 1, 0, 0);
-      eng.add(Rv, reorder(x, {1, 0, 2, 3}), -1, 0, 1);
-      eng.contract("ijae,be->ijab", T, Fvv[s], x, 1.0, 0);
-      eng.add(Rv, x, 1, 0, 1);
-      eng.add(Rv, reorder(x, {0, 1, 3, 2}), -1, 0, 1);
-      eng.contract("imab,mj->ijab", T, Foo[s], x, 1.0, 0);
-      eng.add(Rv, x, -1, 0, 1);
-      eng.add(Rv, reorder(x, {1, 0, 2, 3}), 1, 0, 1);
-      // hole ladder with the T1-T1 piece of the dressed particle ladder
+      View t = t1(Xs, s);
+      for (int64_t i0 = 0; i0 < no; i0 += ci) {
+        const int64_t m = std::min<int64_t>(ci, no - i0);
+        const size_t mr = arena.mark();
+        View x = sstemp({m, no, nv, nv}, s);
+        // dressed <ab||ij> plus Coulomb ring: Lbar_ai Lbar_bj - Lbar_aj Lbar_bi
+        eng.contract("Qai,Qbj->ijab", block(Lbar[s], {0, 0, i0}, {Q, nv, m}), Lbar[s], x, 1.0, 0);
+        accum(Rs, s, x, i0, 0, 1.0, 1, 0);
+        View xt = expand_rows(Xs, s, i0, m);
+        // P(ab) sum_e t_ijae F_be
+        eng.contract("ijae,be->ijab", xt, Fvv[s], x, 1.0, 0);
+        accum(Rs, s, x, i0, 0, 1.0, 0, 1);
+        // -P(ij) sum_m t_imab F_mj
+        eng.contract("imab,mj->ijab", xt, Foo[s], x, 1.0, 0);
+        accum(Rs, s, x, i0, 0, -1.0, 1, 0);
+        arena.release(mr);
+      }
+      const size_t mh = arena.mark();
+      View Tp = tss(Xs, s), Rp = tss(Rs, s);
+      // hole ladder: 1/2 sum_mn t_mnab gA_mnij = sum_{m<n} gA[m<n][i<j] t[m<n][a<b], with
+      // gA_mnij = g_mnij - g_mnji, g = sum_Q L~_mi L~_nj (T1-T1 piece of the ladder)
+      View g = eng.temp({no, no, no, no}, true);
       eng.contract("Qmi,Qnj->mnij", Ldoo[s], Ldoo[s], g, 1.0, 0);
-      eng.add(gA, g, 1, 0, 0);
-      eng.add(gA, reorder(g, {0, 1, 3, 2}), -1, 0, 1);
-      eng.contract("ijef,menf->ijmn", T, Jv, Xo, 1.0, 0);
-      eng.add(tau, T, 1, 0, 0);
-      eng.contract("ia,jb->ijab", t, t, tau, 1.0, 1);
-      eng.contract("ib,ja->ijab", t, t, tau, -1.0, 1);
-      eng.contract("mnab,mnij->ijab", T, gA, Rv, 0.5, 1);
-      eng.contract("mnab,ijmn->ijab", tau, Xo, Rv, 0.5, 1);
-      // Z: -P(ab) sum_m t_ma Z_ij,mb
-      View Zs = make_view(Z3.re + blk * (int64_t)no * no * no * nv, Z3.im + blk * (int64_t)no * no * no * nv,
-                          {no, no, no, nv});
-      eng.contract("ma,ijmb->ijab", t, Zs, x, -1.0, 0);
-      eng.add(Rv, x, 1, 0, 1);
-      eng.add(Rv, reorder(x, {0, 1, 3, 2}), -1, 0, 1);
-      // exchange ring, P(ij) P(ab)
-      eng.set_phase(kPhaseRing);
-      eng.contract("imae,mbej->ijab", T, WX[s][s], x, 1.0, 0);
-      eng.contract("imae,mbej->ijab", TT(Xs, s, u), Vx[u], x, 1.0, 1);
-      eng.set_phase(kPhaseGemm);
-      eng.add(Rv, x, 1, 0, 1);
-      eng.add(Rv, reorder(x, {1, 0, 2, 3}), -1, 0, 1);
-      eng.add(Rv, reorder(x, {0, 1, 3, 2}), -1, 0, 1);
-      eng.add(Rv, reorder(x, {1, 0, 3, 2}), 1, 0, 1);
+      View gA = with_frac(eng.temp({npo(), npo()}, true), {f_po[s], f_po[s]});
+      {
+        SsOp p;
+        p.mode = SsOp::kPackSlab;
+        p.n1 = no; p.n2 = no; p.pair2 = 1; p.i0 = 0; p.ci = no;
+        p.x_re = g.re; p.x_im = g.im; p.y_re = gA.re; p.y_im = gA.im;
+        eng.ss(p);
+      }
+      eng.contract("rp,rq->pq", gA, Tp, Rp, 1.0, 1);
+      // 1/2 sum_mn tau_mnab Xo_ijmn over pairs, Xo_ijmn = sum_ef t_ijef (me|nf)
+      View Xo = with_frac(eng.temp({npo(), npo()}, true), {f_po[s], f_po[s]});
+      eng.contract("pr,rm->pm", Tp, make_view(Jp, nullptr, {npv(), npo()}), Xo, 1.0, 0);
+      View tau = with_frac(eng.temp({npo(), npv()}, true), {f_po[s], f_pv[s]});
+      eng.add(tau, Tp, 1, 0, 0);
+      {
+        SsOp p;
+        p.mode = SsOp::kT1T1;
+        p.n1 = no; p.n2 = nv; p.beta = 1; p.alpha = 1.0;
+        p.y_re = tau.re; p.y_im = tau.im; p.u_re = t.re; p.u_im = t.im;
+        p.pt = tables();
+        eng.ss(p);
+      }
+      eng.contract("pm,mq->pq", Xo, tau, Rp, 1.0, 1);
+      arena.release(mh);
+      // Z: -P(ab) sum_m t_ma Z_ij,mb over pairs i<j (blocks of pair rows)
+      const int64_t cp = std::max<int64_t>(1, std::min<int64_t>(npo(), kPairRowDoubles / std::max<int64_t>(1, 2 * (int64_t)nv * nv)));
+      for (int64_t p0 = 0; p0 < npo(); p0 += cp) {
+        const int64_t m = std::min<int64_t>(cp, npo() - p0);
+        const size_t mr = arena.mark();
+        View y = with_frac(eng.temp({m, nv, nv}, true), {f_po[s], f_v[s], f_v[s]});
+        View Zs = with_frac(make_view(Zp.re + (s * npo() + p0) * nov, Zp.im + (s * npo() + p0) * nov, {m, no, nv}),
+                            {f_po[s], f_o[s], f_v[s]});
+        eng.contract("ma,Pmb->Pab", t, Zs, y, -1.0, 0);
+        SsOp a = ss_op(SsOp::kAccumRows, Rs, s);
+        a.i0 = p0; a.ci = m; a.anti2 = 1;
+        a.x_re = y.re; a.x_im = y.im;
+        eng.ss(a);
+        arena.release(mr);
+      }
     }
-    // alpha-beta doubles
+    // alpha-beta doubles (full storage, accumulated in place)
     {
-      View Rv = t2(Rs, 1), T = t2(Xs, 1);
+      View Rv = tab(Rs), T = tab(Xs);
       View ta = t1(Xs, 0), tb = t1(Xs, 1);
-      eng.contract("Qai,Qbj->ijab", Lbar[0], Lbar[1], Rv, 1.0, 0);
+      eng.contract("Qai,Qbj->ijab", Lbar[0], Lbar[1], Rv, 1.0, 1);
       eng.contract("ijae,be->ijab", T, Fvv[1], Rv, 1.0, 1);
       eng.contract("ae,ijeb->ijab", Fvv[0], T, Rv, 1.0, 1);
       eng.contract("imab,mj->ijab", T, Foo[1], Rv, -1.0, 1);
       eng.contract("mi,mjab->ijab", Foo[0], T, Rv, -1.0, 1);
+      const size_t ma = arena.mark();
+      View g = with_frac(eng.temp({no, no, no, no}, true), {f_o[0], f_o[1], f_o[0], f_o[1]});
+      View Xo = with_frac(eng.temp({no, no, no, no}, true), {f_o[0], f_o[1], f_o[0], f_o[1]});
+      View Y = with_frac(eng.temp({no, no, no, nv}, true), {f_o[0], f_o[1], f_o[0], f_v[1]});
       eng.contract("Qmi,Qnj->mnij", Ldoo[0], Ldoo[1], g, 1.0, 0);
       eng.contract("ijef,menf->ijmn", T, Jv, Xo, 1.0, 0);
-      eng.add(tau, T, 1, 0, 0);
-      eng.contract("ia,jb->ijab", ta, tb, tau, 1.0, 1);
       eng.contract("mnab,mnij->ijab", T, g, Rv, 1.0, 1);
-      eng.contract("mnab,ijmn->ijab", tau, Xo, Rv, 1.0, 1);
-      View Zs = make_view(Z3.re + (int64_t)no * no * no * nv, Z3.im + (int64_t)no * no * no * nv, {no, no, no, nv});
-      eng.contract("ma,ijmb->ijab", ta, Zs, Rv, -1.0, 1);
-      View Z2 = eng.temp({no, no, nv, no}, true);
-      eng.set_phase(kPhaseRing);
-      eng.contract("ijef,fena->ijan", T, Bv, Z2, 1.0, 0);   // sum_ef T_ijef (ae|nf)
-      eng.set_phase(kPhaseGemm);
-      eng.contract("nb,ijan->ijab", tb, Z2, Rv, -1.0, 1);
-      eng.set_phase(kPhaseRing);
-      eng.contract("imae,mbej->ijab", T, WX[1][1], Rv, 1.0, 1);
-      eng.contract("mjae,mbei->ijab", T, WX[0][1], Rv, 1.0, 1);
-      eng.contract("imeb,maej->ijab", T, WX[1][0], Rv, 1.0, 1);
-      eng.contract("mjeb,maei->ijab", T, WX[0][0], Rv, 1.0, 1);
-      eng.contract("imae,mbej->ijab", t2(Xs, 0), Vx[0], Rv, 1.0, 1);
-      eng.contract("jmbe,maei->ijab", t2(Xs, 2), Vx[1], Rv, 1.0, 1);
-      eng.set_phase(kPhaseGemm);
+      // sum_mn tau_mnab Xo_ijmn with tau = t2 + t_ma t_nb
+      eng.contract("mnab,ijmn->ijab", T, Xo, Rv, 1.0, 1);
+      eng.contract("ijmn,nb->ijmb", Xo, tb, Y, 1.0, 0);
+      eng.contract("ma,ijmb->ijab", ta, Y, Rv, 1.0, 1);
+      eng.contract("ma,ijmb->ijab", ta, make_view(Z3ab.re, Z3ab.im, {no, no, no, nv}), Rv, -1.0, 1);
+      eng.contract("nb,ijan->ijab", tb, Z2ab, Rv, -1.0, 1);
+      arena.release(ma);
     }
-    // particle-particle ladder with the real (ae|bf): the alpha-beta block in full
-    // storage, the same-spin blocks as sum_{e<f} T_ijef <ab||ef> over pairs i < j, a < b
-    eng.set_phase(kPhaseLadder);
-    eng.contract("Pef,efab->Pab", Tab, Vl, Rab, 1.0, 1, &conv_v);
-    {
-      const size_t mz = arena.mark();
-      View Zp = eng.temp({2 * npo, npv}, true);
-      eng.contract("Pq,qr->Pr", Tp, make_view(Wpp, nullptr, {npv, npv}), Zp, 1.0, 0, &conv_w);
-      PairOp u = same_spin_pairs(r2, Zp, nv, 1);
-      u.mode = 1;
-      u.beta = 1;
-      eng.pairs(u);
-      arena.release(mz);
-    }
-    eng.set_phase(kPhaseGemm);
-    // zero the amplitudes of spin-orbitals that do not exist
-    {
-      const int sp[3][2] = {{0, 0}, {0, 1}, {1, 1}};
-      for (int b = 0; b < 3; ++b) {
-        const double* sc[4] = {mo[sp[b][0]], mo[sp[b][1]], mv[sp[b][0]], mv[sp[b][1]]};
-        eng.scale(t2(Rs, b), sc);
-      }
-    }
+    mask_set(Rs);
     res_flops = eng.flops;
-    for (int k = 0; k < kNumPhases; ++k) res_phase_flops[k] = eng.phase_flops[k];
+    res_alg_flops = eng.alg_flops;
+    for (int k = 0; k < kNumPhases; ++k) {
+      res_phase_flops[k] = eng.phase_flops[k];
+      res_alg_phase_flops[k] = eng.alg_phase_flops[k];
+    }
     eng.prec = RTEOM_FP64;
     arena.release(mk);
   }
@@ -619,6 +845,7 @@ struct Context {
   UpdateOp update_op(bool start) {
     UpdateOp u;
     u.lay = lay;
+    u.pt = tables();
     u.x_re = X;
     u.x_im = X + lay.size();
     u.r_re = R;
@@ -766,24 +993,6 @@ struct Context {
     }
   }
 
-  // Same-spin doubles are stored in full; keep them antisymmetric in a Jacobi
-  // iteration, whose map amplifies their symmetric part (which the equations never
-  // constrain) from rounding level by ~0.17 e-folds per iteration otherwise.
-  void antisymmetrize_same_spin(double* set) {
-    eng.set_phase(kPhaseMove);
-    for (int b : {0, 2}) {
-      const size_t mk = arena.mark();
-      View T = t2(set, b);
-      View c = eng.temp({no, no, nv, nv}, true);
-      eng.add(c, T, 1.0, 0.0, 0);
-      eng.add(T, c, 0.25, 0.0, 0);
-      eng.add(T, reorder(c, {1, 0, 2, 3}), -0.25, 0.0, 1);
-      eng.add(T, reorder(c, {0, 1, 3, 2}), -0.25, 0.0, 1);
-      eng.add(T, reorder(c, {1, 0, 3, 2}), 0.25, 0.0, 1);
-      arena.release(mk);
-    }
-  }
-
   // Ground-state CCSD (R(T) = 0) by Jacobi iteration from T = 0; e_out = E^corr.
   int ground_state(double tol, int max_iter, double* e_out) {
     be->fill(X, 2 * lay.size(), 0.0);
@@ -796,7 +1005,6 @@ struct Context {
       be->set_phase(kPhaseUpdate);
       be->fill(delta, 1, 0.0);
       be->update(u);
-      antisymmetrize_same_spin(X);
       double d = 0.0;
       be->d2h(&d, delta, sizeof(double));
       if (!std::isfinite(d)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitudes in the ground-state iteration");
@@ -916,7 +1124,15 @@ bool valid_options(const rteom_options* o, std::string* m) {
   if (o->max_steps < 1) { *m = "max_steps must be >= 1"; return false; }
   if (o->tune < 0 || o->tune > 1) { *m = "tune must be 0 or 1"; return false; }
   if (o->fp_anderson < 0 || o->fp_anderson > 8) { *m = "fp_anderson must be in 0..8"; return false; }
+  if (o->plan_slab < 0 || o->plan_block < 0) { *m = "plan_slab and plan_block must be >= 0"; return false; }
   return true;
+}
+
+// Memory limit of the plan: the option (0 = the default), and no more than a caller's workspace.
+size_t plan_limit(const rteom_options& o) {
+  size_t lim = o.mem_limit ? o.mem_limit : rteom::kDefaultMemLimit;
+  if (o.workspace) lim = std::min(lim, o.workspace_bytes);
+  return lim;
 }
 
 rteom_status check_sizes(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol,
@@ -949,28 +1165,70 @@ void rteom_default_options(rteom_options* o) {
   o->tune = 1;
 }
 
-// Plan init + one residual without touching a device: the workspace peak and the
-// residual's flop counts (total and by phase).
-static rteom_status dry_plan(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol,
-                             int32_t core_orb, int32_t core_spin, const rteom_options& o, size_t* bytes,
-                             double* flops, double* phase_flops) {
+// What one dry run of init + one residual (no device work) gives.
+struct PlanResult {
+  rteom::Plan plan;
+  size_t bytes = 0;
+  double flops = 0.0, alg_flops = 0.0;
+  double phase_flops[rteom::kNumPhases] = {0}, alg_phase_flops[rteom::kNumPhases] = {0};
+};
+
+static rteom_status dry_run(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol, int32_t core_orb,
+                            int32_t core_spin, const rteom_options& o, const rteom::Plan& plan, PlanResult* r) {
   std::unique_ptr<rteom_ctx> ctx(new rteom_ctx());
   Context& c = ctx->c;
   c.dry = true;
   c.opt = o;
+  c.plan = plan;
   c.n = n_orb; c.nq = n_chol; c.na = n_occ_a; c.nb = n_occ_b; c.core_orb = core_orb; c.core_spin = core_spin;
   c.arena.init(nullptr, ~static_cast<size_t>(0) >> 2);
   const rteom_status st = guarded(ctx.get(), [&] {
     c.init(nullptr, nullptr);
     c.residual(c.X, c.R);
-    c.antisymmetrize_same_spin(c.X);   // its temporary, for rteom_ground_state
   });
   if (st != RTEOM_OK) { g_last_error = c.err; return st; }
-  *bytes = c.arena.peak() + (1 << 20);
-  if (flops) *flops = c.res_flops;
-  if (phase_flops)
-    for (int k = 0; k < rteom::kNumPhases; ++k) phase_flops[k] = c.res_phase_flops[k];
+  r->plan = plan;
+  r->bytes = c.arena.peak() + (1 << 20);
+  r->flops = c.res_flops;
+  r->alg_flops = c.res_alg_flops;
+  for (int k = 0; k < rteom::kNumPhases; ++k) {
+    r->phase_flops[k] = c.res_phase_flops[k];
+    r->alg_phase_flops[k] = c.res_alg_phase_flops[k];
+  }
   return RTEOM_OK;
+}
+
+// The plan of the largest blocks whose workspace fits the memory limit: the integral
+// blocks resident and no blocking if possible, then smaller ring and row blocks, then
+// integral slabs rebuilt per residual (largest slab first).
+static rteom_status choose_plan(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol, int32_t core_orb,
+                                int32_t core_spin, const rteom_options& o, PlanResult* out) {
+  const size_t lim = plan_limit(o);
+  const int64_t all = int64_t(1) << 30;
+  std::vector<rteom::Plan> cands;
+  if (o.plan_slab > 0 || o.plan_block > 0) {
+    const int64_t c = o.plan_block > 0 ? o.plan_block : all;
+    cands.push_back({o.plan_slab == 0, (int64_t)o.plan_slab, c, c});
+  } else {
+    for (int64_t c : {all, int64_t(32), int64_t(16), int64_t(8), int64_t(4), int64_t(2), int64_t(1)})
+      cands.push_back({true, 0, c, c});
+    const int64_t slab[][2] = {{16, 16}, {8, 8}, {16, 8}, {8, 4}, {4, 4}, {2, 2}, {1, 1}};
+    for (const auto& x : slab) cands.push_back({false, x[0], x[1], x[1]});
+  }
+  size_t smallest = ~size_t(0);
+  for (const rteom::Plan& p : cands) {
+    PlanResult r;
+    const rteom_status st = dry_run(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, p, &r);
+    if (st != RTEOM_OK) return st;
+    if (r.bytes <= lim) {
+      *out = r;
+      return RTEOM_OK;
+    }
+    smallest = std::min(smallest, r.bytes);
+  }
+  g_last_error = "no plan fits the memory limit of " + std::to_string(lim) + " bytes (smallest needs " +
+                 std::to_string(smallest) + ")";
+  return RTEOM_ERR_OOM;
 }
 
 rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b, int32_t n_chol,
@@ -984,7 +1242,10 @@ rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ
   rteom_default_options(&o);
   if (opt) o = *opt;
   if (!valid_options(&o, &m)) { g_last_error = m; return RTEOM_ERR_ARG; }
-  return dry_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, bytes, nullptr, nullptr);
+  PlanResult r;
+  st = choose_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, &r);
+  if (st == RTEOM_OK) *bytes = r.bytes;
+  return st;
 }
 
 rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
@@ -1017,15 +1278,20 @@ rteom_status rteom_init(rteom_ctx** out, int32_t n_orb, int32_t n_occ_a, int32_t
           return RTEOM_ERR_ARG;
         }
       }
-  size_t need = 0;
-  double plan_flops = 0.0, plan_phase_flops[rteom::kNumPhases] = {0};
-  st = dry_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, &need, &plan_flops, plan_phase_flops);
+  PlanResult pr;
+  st = choose_plan(n_orb, n_occ_a, n_occ_b, n_chol, core_orb, core_spin, o, &pr);
   if (st != RTEOM_OK) return st;
+  const size_t need = pr.bytes;
   std::unique_ptr<rteom_ctx> ctx(new rteom_ctx());
   Context& c = ctx->c;
   c.opt = o;
-  c.res_flops = plan_flops;       // known from the plan before the first evaluation
-  for (int k = 0; k < rteom::kNumPhases; ++k) c.res_phase_flops[k] = plan_phase_flops[k];
+  c.plan = pr.plan;
+  c.res_flops = pr.flops;         // known from the plan before the first evaluation
+  c.res_alg_flops = pr.alg_flops;
+  for (int k = 0; k < rteom::kNumPhases; ++k) {
+    c.res_phase_flops[k] = pr.phase_flops[k];
+    c.res_alg_phase_flops[k] = pr.alg_phase_flops[k];
+  }
   c.n = n_orb; c.nq = n_chol; c.na = n_occ_a; c.nb = n_occ_b; c.core_orb = core_orb; c.core_spin = core_spin;
   std::string berr;
 #ifdef RTEOM_HOST_BACKEND
@@ -1115,7 +1381,7 @@ rteom_status rteom_cumulant(const rteom_ctx* cctx, int64_t cap, double* t_out, d
 
 namespace {
 constexpr uint64_t kImageMagic = 0x4d4f4554522d5452ull;   // "RT-RTEOM" little-endian
-constexpr uint32_t kImageVersion = 1;
+constexpr uint32_t kImageVersion = 2;   // 2: same-spin doubles in pair storage
 struct ImageHeader {
   uint64_t magic;
   uint32_t version, reserved;
@@ -1276,15 +1542,7 @@ rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double
     for (double v : buf)
       if (!std::isfinite(v)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitude");
     c.be->h2d(c.X, buf.data(), buf.size() * sizeof(double));
-    for (int s = 0; s < 2; ++s) {
-      const double* sc[2] = {c.mo[s], c.mv[s]};
-      c.eng.scale(c.t1(c.X, s), sc);
-    }
-    const int sp[3][2] = {{0, 0}, {0, 1}, {1, 1}};
-    for (int b = 0; b < 3; ++b) {
-      const double* sc[4] = {c.mo[sp[b][0]], c.mo[sp[b][1]], c.mv[sp[b][0]], c.mv[sp[b][1]]};
-      c.eng.scale(c.t2(c.X, b), sc);
-    }
+    c.mask_set(c.X);
     c.energy(c.X, c.e_hist + 2 * c.nsteps);   // E(T_n) for the next trapezoid
     c.be->fill(c.dbad, 1, 0.0);
     c.failed = false;
@@ -1333,7 +1591,20 @@ rteom_status rteom_energy(rteom_ctx* ctx, double* e_out) {
 
 rteom_status rteom_residual_flops(const rteom_ctx* cctx, double* flops) {
   if (!cctx || !flops) { g_last_error = "bad argument"; return RTEOM_ERR_ARG; }
-  *flops = cctx->c.res_flops;
+  *flops = cctx->c.res_alg_flops;
+  return RTEOM_OK;
+}
+
+rteom_status rteom_plan_info(const rteom_ctx* cctx, int32_t* resident, int64_t* e_slab, int64_t* ring_cols,
+                             int64_t* rows, double* exec_flops, size_t* workspace_bytes) {
+  if (!cctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  const Context& c = cctx->c;
+  if (resident) *resident = c.plan.resident ? 1 : 0;
+  if (e_slab) *e_slab = c.plan.resident ? c.nv : std::min<int64_t>(c.plan.es, c.nv);
+  if (ring_cols) *ring_cols = std::min<int64_t>(c.plan.cj, c.no);
+  if (rows) *rows = std::min<int64_t>(c.plan.ci, c.no);
+  if (exec_flops) *exec_flops = c.res_flops;
+  if (workspace_bytes) *workspace_bytes = c.arena.capacity();
   return RTEOM_OK;
 }
 
@@ -1352,7 +1623,7 @@ rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double
     const double t = c.be->phase_ms(phase, &n);
     if (ms) *ms = t;
     if (ops) *ops = n;
-    if (flops) *flops = c.res_phase_flops[phase];
+    if (flops) *flops = c.res_alg_phase_flops[phase];
   });
 }
 

@@ -23,10 +23,11 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
     "rteom_spectral", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
-    "rteom_residual_flops", "rteom_profile", "rteom_phase_stats", "rteom_batch_create", "rteom_batch_step",
+    "rteom_residual_flops", "rteom_plan_info", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
+    "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
-PHASES = ("ladder", "ring", "gemm", "move", "update", "energy")
+PHASES = ("ladder", "ring", "gemm", "move", "update", "energy", "build")
 
 
 class RteomError(RuntimeError):
@@ -51,6 +52,9 @@ class Options(ctypes.Structure):
         ("workspace_bytes", ctypes.c_size_t),
         ("tune", ctypes.c_int32),
         ("fp_anderson", ctypes.c_int32),
+        ("mem_limit", ctypes.c_size_t),
+        ("plan_slab", ctypes.c_int32),
+        ("plan_block", ctypes.c_int32),
     ]
 
 
@@ -92,6 +96,8 @@ def load(path: str = LIB_PATH):
     lib.rteom_residual.argtypes = [c.c_void_p, _dp, _dp]
     lib.rteom_energy.argtypes = [c.c_void_p, _dp]
     lib.rteom_residual_flops.argtypes = [c.c_void_p, _dp]
+    lib.rteom_plan_info.argtypes = [c.c_void_p, _ip, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
+                                    c.POINTER(c.c_int64), _dp, c.POINTER(c.c_size_t)]
     lib.rteom_profile.argtypes = [c.c_void_p, c.c_uint32]
     lib.rteom_phase_stats.argtypes = [c.c_void_p, c.c_int32, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_batch_create.argtypes = [c.POINTER(c.c_void_p), c.c_int32, c.POINTER(c.c_void_p)]
@@ -111,12 +117,40 @@ def _ptr(a):
     return a.ctypes.data_as(_dp) if a is not None else None
 
 
+def pair_index(n):
+    """(first, second) index arrays of the pairs i < j of n in the ABI's lexicographic order."""
+    i, j = np.triu_indices(n, 1)
+    return i, j
+
+
+def pack_same_spin(full):
+    """[n1][n1][n2][n2] antisymmetric block -> its pair storage [P1][P2] (elements i < j, a < b)."""
+    n1, n2 = full.shape[0], full.shape[2]
+    i, j = pair_index(n1)
+    a, b = pair_index(n2)
+    return np.ascontiguousarray(full[i, j][:, a, b])
+
+
+def expand_same_spin(pairs, n1, n2):
+    """Pair storage [P1][P2] -> the full antisymmetric block [n1][n1][n2][n2] (layout only:
+    each stored element and its sign-flipped images)."""
+    out = np.zeros((n1, n1, n2, n2), dtype=pairs.dtype)
+    i, j = pair_index(n1)
+    a, b = pair_index(n2)
+    blk = np.zeros((len(i), n2, n2), dtype=pairs.dtype)
+    blk[:, a, b] = pairs
+    blk[:, b, a] = -pairs
+    out[i, j] = blk
+    out[j, i] = -blk
+    return out
+
+
 class Propagator:
     """One core-hole propagation (rteom_init ... rteom_free)."""
 
     def __init__(self, eps, chol, n_occ_a, n_occ_b, core_orb=0, core_spin=1, prec="fp64", fp_map=0,
                  fixed_iters=0, max_iter=50, tol=1e-10, include_ft1=True, max_steps=100000,
-                 stream=None, workspace=None, graph=False, tune=True, anderson=0, lib_path=LIB_PATH):
+                 stream=None, workspace=None, graph=False, tune=True, anderson=0, mem_limit=0, plan_slab=0, plan_block=0, lib_path=LIB_PATH):
         self.lib = load(lib_path)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         chol = np.ascontiguousarray(chol, dtype=np.float64)
@@ -134,6 +168,9 @@ class Propagator:
         opt.graph = 1 if graph else 0
         opt.tune = 1 if tune else 0
         opt.fp_anderson = int(anderson)
+        opt.mem_limit = int(mem_limit)
+        opt.plan_slab = int(plan_slab)
+        opt.plan_block = int(plan_block)
         opt.stream = stream
         self._ws = None
         if workspace == "torch":
@@ -170,12 +207,47 @@ class Propagator:
             msg = self.lib.rteom_last_error(h)
             raise RteomError(st, msg.decode() if msg else "")
 
-    # -- amplitude layout helpers (host)
+    # -- amplitude layout helpers (host; include/rteom.h): t1 [2][n_o][n_v], t2 = the two
+    # same-spin blocks in pair storage [2][P_o][P_v] followed by the alpha-beta block
+    # [n_o][n_o][n_v][n_v].  Methods take and return t2 either as that pair (tss, tab) or,
+    # with full=True, as the antisymmetric full blocks [3][n_o][n_o][n_v][n_v] (aa, ab, bb).
     def t1_shape(self):
         return (2, self.no, self.nv)
 
     def t2_shape(self):
         return (3, self.no, self.no, self.nv, self.nv)
+
+    def _t2_flat(self, t2):
+        no, nv = self.no, self.nv
+        if isinstance(t2, tuple):
+            tss, tab = t2
+        else:
+            t2 = np.asarray(t2)
+            tss = np.stack([pack_same_spin(t2[0]), pack_same_spin(t2[2])])
+            tab = t2[1]
+        po, pv = no * (no - 1) // 2, nv * (nv - 1) // 2
+        tss = np.asarray(tss, dtype=np.complex128).reshape(2 * po * pv)
+        tab = np.asarray(tab, dtype=np.complex128).reshape(no * no * nv * nv)
+        return np.ascontiguousarray(np.concatenate([tss, tab]))
+
+    def _t2_out(self, flat, full):
+        no, nv = self.no, self.nv
+        po, pv = no * (no - 1) // 2, nv * (nv - 1) // 2
+        tss = flat[: 2 * po * pv].reshape(2, po, pv)
+        tab = flat[2 * po * pv:].reshape(no, no, nv, nv)
+        if not full:
+            return tss, tab
+        return np.stack([expand_same_spin(tss[0], no, nv), tab, expand_same_spin(tss[1], no, nv)])
+
+    def plan(self):
+        """The memory plan rteom_init chose (rteom_plan_info)."""
+        res, es, cj, ci = ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        fl, ws = ctypes.c_double(), ctypes.c_size_t()
+        st = self.lib.rteom_plan_info(self.h, ctypes.byref(res), ctypes.byref(es), ctypes.byref(cj), ctypes.byref(ci),
+                                      ctypes.byref(fl), ctypes.byref(ws))
+        self._check(st, self.h)
+        return {"resident": bool(res.value), "e_slab": es.value, "ring_cols": cj.value, "rows": ci.value,
+                "exec_flops": fl.value, "workspace_bytes": ws.value}
 
     def step(self, dt, n_steps=1):
         iters = np.zeros(max(n_steps, 1), dtype=np.int32)
@@ -229,32 +301,36 @@ class Propagator:
         self._check(st, self.h)
         return a, qp[0], qp[1]
 
+    def _n2(self):
+        no, nv = self.no, self.nv
+        return no * (no - 1) * nv * (nv - 1) // 2 + no * no * nv * nv
+
     def set_amplitudes(self, t1, t2):
         t1 = np.ascontiguousarray(t1, dtype=np.complex128).reshape(self.t1_shape())
-        t2 = np.ascontiguousarray(t2, dtype=np.complex128).reshape(self.t2_shape())
+        t2 = self._t2_flat(t2)
         st = self.lib.rteom_set_amplitudes(self.h, t1.view(np.float64).ctypes.data_as(_dp),
                                            t2.view(np.float64).ctypes.data_as(_dp))
         self._check(st, self.h)
 
-    def get_amplitudes(self):
+    def get_amplitudes(self, full=True):
         t1 = np.zeros(self.t1_shape(), dtype=np.complex128)
-        t2 = np.zeros(self.t2_shape(), dtype=np.complex128)
+        t2 = np.zeros(self._n2(), dtype=np.complex128)
         st = self.lib.rteom_get_amplitudes(self.h, t1.view(np.float64).ctypes.data_as(_dp),
                                            t2.view(np.float64).ctypes.data_as(_dp))
         self._check(st, self.h)
-        return t1, t2
+        return t1, self._t2_out(t2, full)
 
-    def residual(self, want=True):
+    def residual(self, want=True, full=True):
         if not want:
             st = self.lib.rteom_residual(self.h, None, None)
             self._check(st, self.h)
             return None
         r1 = np.zeros(self.t1_shape(), dtype=np.complex128)
-        r2 = np.zeros(self.t2_shape(), dtype=np.complex128)
+        r2 = np.zeros(self._n2(), dtype=np.complex128)
         st = self.lib.rteom_residual(self.h, r1.view(np.float64).ctypes.data_as(_dp),
                                      r2.view(np.float64).ctypes.data_as(_dp))
         self._check(st, self.h)
-        return r1, r2
+        return r1, self._t2_out(r2, full)
 
     def energy(self):
         e = np.zeros(2)

@@ -75,6 +75,7 @@ class HostBackend : public Backend {
         if (p.scale[d]) s *= p.scale[d][idx[d]];
       vr[t] = s * (p.alpha_re * xr - p.alpha_im * xi);
       vi[t] = s * (p.alpha_re * xi + p.alpha_im * xr);
+      if (p.alpha_re == 0.0 && p.alpha_im == 0.0) vr[t] = vi[t] = 0.0;
     }
     for (int64_t t = 0; t < total; ++t) {
       int64_t r = t;
@@ -88,45 +89,106 @@ class HostBackend : public Backend {
     }
   }
 
-  void pairs(const PairOp& op) override {
-    const int64_t n1 = op.n1, n2 = op.n2;
-    const int64_t rest = op.pair2 ? n2 * n2 : n2;
-    const int64_t nq = op.pair2 ? n2 * (n2 - 1) / 2 : n2;
-    auto pidx = [](int64_t i, int64_t j, int64_t n) { return i * (2 * n - i - 1) / 2 + (j - i - 1); };
-    for (int64_t blk = 0; blk < op.nblk; ++blk)
-      for (int64_t i = 0; i < n1; ++i)
-        for (int64_t j = 0; j < n1; ++j)
-          for (int64_t c = 0; c < rest; ++c) {
-            const int64_t a = op.pair2 ? c / n2 : 0, b = op.pair2 ? c % n2 : c;
-            const int64_t xo = blk * op.x_bs + (i * n1 + j) * rest + c;
-            if (op.mode == 0) {
-              if (i >= j || (op.pair2 && a >= b)) continue;
-              const int64_t yo = blk * op.y_bs + pidx(i, j, n1) * nq + (op.pair2 ? pidx(a, b, n2) : b);
-              const int64_t xs = blk * op.x_bs + (j * n1 + i) * rest + c;
-              op.y_re[yo] = op.alpha * (op.x_re[xo] - (op.anti ? op.x_re[xs] : 0.0));
-              if (op.y_im) op.y_im[yo] = op.alpha * (op.x_im[xo] - (op.anti ? op.x_im[xs] : 0.0));
-            } else {
-              double vr = 0.0, vi = 0.0;
-              if (i != j && (!op.pair2 || a != b)) {
-                double sg = i < j ? 1.0 : -1.0;
-                int64_t q = b;
-                if (op.pair2) {
-                  q = pidx(std::min(a, b), std::max(a, b), n2);
-                  if (b < a) sg = -sg;
+  void ss(const SsOp& op) override {
+    const int64_t n1 = op.n1, n2 = op.n2, np1 = npairs(n1), np2 = npairs(n2);
+    auto pidx = [](int64_t i, int64_t j, int64_t n) { return pair_start(i, n) + j - i - 1; };
+    const bool cx = op.y_im != nullptr || op.x_im != nullptr;
+    auto X = [&](int pl, int64_t o) { return pl ? op.x_im[o] : op.x_re[o]; };
+    double* Y[2] = {op.y_re, op.y_im};
+    double* Xw[2] = {op.x_re, op.x_im};
+    const int npl = cx ? 2 : 1;
+    switch (op.mode) {
+      case SsOp::kExpand:
+        for (int64_t ii = 0; ii < op.ci; ++ii)
+          for (int64_t jj = 0; jj < op.cj; ++jj)
+            for (int64_t a = 0; a < n2; ++a)
+              for (int64_t b = 0; b < n2; ++b) {
+                const int64_t i = op.i0 + ii, j = op.j0 + jj, xo = ((ii * op.cj + jj) * n2 + a) * n2 + b;
+                for (int pl = 0; pl < npl; ++pl) {
+                  double v = 0.0;
+                  if (i != j && a != b) {
+                    const double sg = (i < j ? 1.0 : -1.0) * (a < b ? 1.0 : -1.0);
+                    v = op.alpha * sg * Y[pl][pidx(std::min(i, j), std::max(i, j), n1) * np2 +
+                                              pidx(std::min(a, b), std::max(a, b), n2)];
+                  }
+                  Xw[pl][xo] = v + (op.beta ? Xw[pl][xo] : 0.0);
                 }
-                const int64_t yo = blk * op.y_bs + pidx(std::min(i, j), std::max(i, j), n1) * nq + q;
-                vr = op.alpha * sg * op.y_re[yo];
-                if (op.y_im) vi = op.alpha * sg * op.y_im[yo];
               }
-              op.x_re[xo] = vr + (op.beta ? op.x_re[xo] : 0.0);
-              if (op.x_im) op.x_im[xo] = vi + (op.beta ? op.x_im[xo] : 0.0);
+        break;
+      case SsOp::kAccum: {
+        // the definition: the block's antisymmetrised contributions, pair by pair
+        auto in_i = [&](int64_t k) { return k >= op.i0 && k < op.i0 + op.ci; };
+        auto in_j = [&](int64_t k) { return k >= op.j0 && k < op.j0 + op.cj; };
+        auto xv = [&](int pl, int64_t i, int64_t j, int64_t a, int64_t b) {
+          return X(pl, (((i - op.i0) * op.cj + (j - op.j0)) * n2 + a) * n2 + b);
+        };
+        for (int64_t k = 0; k < n1; ++k)
+          for (int64_t l = k + 1; l < n1; ++l)
+            for (int64_t a = 0; a < n2; ++a)
+              for (int64_t b = a + 1; b < n2; ++b)
+                for (int pl = 0; pl < npl; ++pl) {
+                  double v = 0.0;
+                  if (in_i(k) && in_j(l)) v += xv(pl, k, l, a, b) - (op.anti2 ? xv(pl, k, l, b, a) : 0.0);
+                  if (op.anti1 && in_i(l) && in_j(k)) v -= xv(pl, l, k, a, b) - (op.anti2 ? xv(pl, l, k, b, a) : 0.0);
+                  Y[pl][pidx(k, l, n1) * np2 + pidx(a, b, n2)] += op.alpha * v;
+                }
+        break;
+      }
+      case SsOp::kAccumRows:
+        for (int64_t pp = 0; pp < op.ci; ++pp)
+          for (int64_t a = 0; a < n2; ++a)
+            for (int64_t b = a + 1; b < n2; ++b)
+              for (int pl = 0; pl < npl; ++pl) {
+                const double v = X(pl, (pp * n2 + a) * n2 + b) - (op.anti2 ? X(pl, (pp * n2 + b) * n2 + a) : 0.0);
+                Y[pl][(op.i0 + pp) * np2 + pidx(a, b, n2)] += op.alpha * v;
+              }
+        break;
+      case SsOp::kT1T1:
+        for (int64_t p = 0; p < np1; ++p)
+          for (int64_t q = 0; q < np2; ++q) {
+            const int64_t i = op.pt.oi[p], j = op.pt.oj[p], a = op.pt.va[q], b = op.pt.vb[q];
+            auto ur = [&](int64_t x, int64_t y) { return op.u_re[x * n2 + y]; };
+            auto ui = [&](int64_t x, int64_t y) { return op.u_im[x * n2 + y]; };
+            const double vr = ur(i, a) * ur(j, b) - ui(i, a) * ui(j, b) - (ur(i, b) * ur(j, a) - ui(i, b) * ui(j, a));
+            const double vi = ur(i, a) * ui(j, b) + ui(i, a) * ur(j, b) - (ur(i, b) * ui(j, a) + ui(i, b) * ur(j, a));
+            const int64_t o = p * np2 + q;
+            op.y_re[o] = op.alpha * vr + (op.beta ? op.y_re[o] : 0.0);
+            op.y_im[o] = op.alpha * vi + (op.beta ? op.y_im[o] : 0.0);
+          }
+        break;
+      case SsOp::kMask:
+        for (int64_t p = 0; p < np1; ++p)
+          for (int64_t q = 0; q < np2; ++q) {
+            const double m = op.m1[op.pt.oi[p]] * op.m1[op.pt.oj[p]] * op.m2[op.pt.va[q]] * op.m2[op.pt.vb[q]];
+            for (int pl = 0; pl < npl; ++pl) Y[pl][p * np2 + q] *= m;
+          }
+        break;
+      case SsOp::kPackSlab: {
+        const int64_t base = pair_start(op.i0, n1);
+        const int64_t rest = op.pair2 ? n2 * n2 : n2, nq = op.pair2 ? np2 : n2;
+        for (int64_t ee = 0; ee < op.ci; ++ee)
+          for (int64_t f = op.i0 + ee + 1; f < n1; ++f) {
+            const int64_t p = pidx(op.i0 + ee, f, n1) - base;
+            const int64_t xo = (ee * n1 + f) * rest;
+            for (int pl = 0; pl < npl; ++pl) {
+              if (op.pair2) {
+                for (int64_t a = 0; a < n2; ++a)
+                  for (int64_t b = a + 1; b < n2; ++b)
+                    Y[pl][p * nq + pidx(a, b, n2)] = op.alpha * (X(pl, xo + a * n2 + b) - X(pl, xo + b * n2 + a));
+              } else {
+                for (int64_t c = 0; c < n2; ++c) Y[pl][p * nq + c] = op.alpha * X(pl, xo + c);
+              }
             }
           }
+        break;
+      }
+    }
   }
 
   void update(const UpdateOp& u) override {
-    const int64_t n1 = u.lay.n1(), n2 = u.lay.n2(), no = u.lay.no, nv = u.lay.nv;
-    const int64_t total = u.lay.size();
+    const int64_t n1 = u.lay.n1(), nss = u.lay.nss(), nab = u.lay.nab(), no = u.lay.no, nv = u.lay.nv;
+    const int64_t npv = u.lay.npv(), total = u.lay.size();
+    (void)nab;
     double dmax = 0.0;
     for (int64_t k = 0; k < total; ++k) {
       double mask, dd;
@@ -135,16 +197,20 @@ class HostBackend : public Backend {
         const int64_t r = k % n1, i = r / nv, a = r % nv;
         mask = u.sv.mo[s][i] * u.sv.mv[s][a];
         dd = u.sv.fo[s][i] - u.sv.fv[s][a];
-      } else {
+      } else if (k < u.lay.off_ab()) {
         const int64_t k2 = k - 2 * n1;
-        const int blk = (int)(k2 / n2);
-        const int s1 = blk == 2 ? 1 : 0, s2 = blk == 0 ? 0 : 1;
-        int64_t r = k2 % n2;
+        const int s = (int)(k2 / nss);
+        const int64_t r = k2 % nss, p = r / npv, q = r % npv;
+        const int64_t i = u.pt.oi[p], j = u.pt.oj[p], a = u.pt.va[q], b = u.pt.vb[q];
+        mask = u.sv.mo[s][i] * u.sv.mo[s][j] * u.sv.mv[s][a] * u.sv.mv[s][b];
+        dd = u.sv.fo[s][i] + u.sv.fo[s][j] - u.sv.fv[s][a] - u.sv.fv[s][b];
+      } else {
+        int64_t r = k - u.lay.off_ab();
         const int64_t b = r % nv; r /= nv;
         const int64_t a = r % nv; r /= nv;
         const int64_t j = r % no, i = r / no;
-        mask = u.sv.mo[s1][i] * u.sv.mo[s2][j] * u.sv.mv[s1][a] * u.sv.mv[s2][b];
-        dd = u.sv.fo[s1][i] + u.sv.fo[s2][j] - u.sv.fv[s1][a] - u.sv.fv[s2][b];
+        mask = u.sv.mo[0][i] * u.sv.mo[1][j] * u.sv.mv[0][a] * u.sv.mv[1][b];
+        dd = u.sv.fo[0][i] + u.sv.fo[1][j] - u.sv.fv[0][a] - u.sv.fv[1][b];
       }
       const double xr = u.x_re[k], xi = u.x_im[k], rr = u.r_re[k], ri = u.r_im[k];
       if (u.mode == 2) {   // Jacobi step towards R(T) = 0
@@ -190,7 +256,8 @@ class HostBackend : public Backend {
   }
 
   void energy(const EnergyOp& e) override {
-    const int64_t no = e.lay.no, nv = e.lay.nv, n1 = e.lay.n1(), n2 = e.lay.n2();
+    const int64_t no = e.lay.no, nv = e.lay.nv, n1 = e.lay.n1(), npv = e.lay.npv();
+    auto pidx = [](int64_t i, int64_t j, int64_t n) { return pair_start(i, n) + j - i - 1; };
     const double* xr = e.x_re;
     const double* xi = e.x_im;
     auto t1r = [&](int s, int64_t i, int64_t a) { return xr[s * n1 + i * nv + a]; };
@@ -209,11 +276,15 @@ class HostBackend : public Backend {
         for (int64_t j = 0; j < no; ++j)
           for (int64_t b = 0; b < nv; ++b) {
             const double J = e.jov[((i * nv + a) * no + j) * nv + b];
-            const int64_t p = ((i * no + j) * nv + a) * nv + b;
-            double wr = 0.0, wi = 0.0;
-            // 1/2 (T_aa + T_bb) + T_ab
-            wr += 0.5 * (xr[2 * n1 + p] + xr[2 * n1 + 2 * n2 + p]) + xr[2 * n1 + n2 + p];
-            wi += 0.5 * (xi[2 * n1 + p] + xi[2 * n1 + 2 * n2 + p]) + xi[2 * n1 + n2 + p];
+            const int64_t p = e.lay.off_ab() + ((i * no + j) * nv + a) * nv + b;
+            double wr = xr[p], wi = xi[p];
+            // 1/2 (T_aa + T_bb) + T_ab, the same-spin elements from pair storage
+            if (i != j && a != b) {
+              const double sg = 0.5 * (i < j ? 1.0 : -1.0) * (a < b ? 1.0 : -1.0);
+              const int64_t q = pidx(std::min(i, j), std::max(i, j), no) * npv + pidx(std::min(a, b), std::max(a, b), nv);
+              wr += sg * (xr[e.lay.off_ss(0) + q] + xr[e.lay.off_ss(1) + q]);
+              wi += sg * (xi[e.lay.off_ss(0) + q] + xi[e.lay.off_ss(1) + q]);
+            }
             for (int s = 0; s < 2; ++s) {
               // 1/2 t_ia t_jb - 1/2 t_ib t_ja (same spin)
               double ar = t1r(s, i, a), ai = t1i(s, i, a), br = t1r(s, j, b), bi = t1i(s, j, b);

@@ -1,8 +1,8 @@
 // Kernel probe (test program, GPU): the GEMM backend on every operand layout,
 // complex combination, ragged size, split-K, broadcast batch and tile shape
 // (forced), against host loops; tile shapes and the converted-operand paths must
-// agree bitwise.  Also the permute kernels against host loops.  "bench" times the
-// tile shapes on large shapes.
+// agree bitwise.  Also the permute kernels and the same-spin pair operations against
+// host loops.
 #include <cstdio>
 #include <cstdlib>
 #include <cmath>
@@ -96,60 +96,6 @@ static int check(Backend* be) {
 // Timing of each tile shape: (M, N, K, a complex, b complex, a k-contiguous, b
 // k-contiguous, largest split-K factor tried); operands hold only their real planes
 // when real.
-static void bench(Backend* be, int min_prec, int max_prec) {
-  struct S { long M, N, K; bool ac, bc, akc, bkc; int max_split; const char* what; };
-  S shapes[] = {
-    {1296, 105625, 105625, true, false, true, false, 1, "alpha-beta ladder (Pef,efab->Pab)"},
-    {1260, 52650, 52650, true, false, true, false, 1, "same-spin ladder in pair storage"},
-    {11700, 11700, 11700, true, true, true, false, 1, "ring cc"},
-    {11700, 11700, 11700, true, false, true, false, 1, "ring cr"},
-    {1296, 105625, 2000, false, false, false, false, 1, "Qmj,Qbe real"},
-    {1296, 11700, 105625, true, false, true, false, 1, "Z (Pef,efmb->Pmb), alpha-beta"},
-    {192, 12321, 12321, true, false, true, false, 1, "formaldehyde ladder"},
-  };
-  for (int prec = min_prec; prec <= max_prec; ++prec)
-  for (auto& s : shapes) {
-    if (prec > 0 && s.max_split > 1 && s.N > 60000) continue;   // the float64 timing is the one needed
-    long na = s.M * s.K, nb = s.K * s.N, nc = s.M * s.N;
-    const long pa = s.ac ? 2 : 1, pb = s.bc ? 2 : 1, pc = (s.ac || s.bc) ? 2 : 1;
-    double *dA = (double*)be->alloc(8 * pa * na), *dB = (double*)be->alloc(8 * pb * nb), *dC = (double*)be->alloc(8 * pc * nc);
-    if (!dA || !dB || !dC) { printf("alloc failed\n"); return; }
-    be->fill(dA, pa * na, 0.001); be->fill(dB, pb * nb, 0.002); be->fill(dC, pc * nc, 0.0);
-    GemmOp g; g.M = s.M; g.N = s.N; g.K = s.K; g.batch = 1;
-    g.a_sm = s.akc ? s.K : 1; g.a_sk = s.akc ? 1 : s.M; g.a_sb = 0;
-    g.b_sk = s.bkc ? 1 : s.N; g.b_sn = s.bkc ? s.K : 1; g.b_sb = 0;
-    g.c_sm = s.N; g.c_sn = 1; g.c_sb = 0; g.alpha = 1.0; g.beta = 0; g.prec = prec;
-    g.a_re = dA; g.a_im = s.ac ? dA + na : nullptr; g.b_re = dB; g.b_im = s.bc ? dB + nb : nullptr;
-    g.c_re = dC; g.c_im = (s.ac || s.bc) ? dC + nc : nullptr;
-    const double mult = (s.ac && s.bc) ? 4.0 : ((s.ac || s.bc) ? 2.0 : 1.0);
-    const double flops = 2.0 * mult * s.M * s.N * s.K;
-    double* dS = nullptr;
-    if (prec >= 1) { dS = (double*)be->alloc(8 * split_doubles(s.M, s.N, s.K, 1, 1, s.ac, s.bc, prec)); g.split = dS; }
-    double* dP = s.max_split > 1 ? (double*)be->alloc(8 * pc * s.max_split * nc) : nullptr;
-    for (int sk = 1; sk <= s.max_split; sk *= 2)
-    for (int v = 0; v < (prec == 0 ? 6 : 4); ++v) {
-      if (sk > 1 && v != 1 && v != 4) continue;
-      g.splitk = sk;
-      g.partial = sk > 1 ? dP : nullptr;
-      be->force_tile(v);
-      be->gemm(g); be->sync();   // warm
-      auto t0 = std::chrono::steady_clock::now();
-      be->gemm(g); be->sync();
-      double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      printf("prec=%d tile=%d split=%d %-36s M=%ld N=%ld K=%ld  %.3f ms  %.1f TFLOP/s\n", prec, v, sk, s.what, s.M, s.N,
-             s.K, sec * 1e3, flops / sec / 1e12);
-      fflush(stdout);
-    }
-    be->force_tile(-1);
-    std::string m;
-    if (!be->ok(&m)) { printf("backend error %s\n", m.c_str()); return; }
-    be->release(dA); be->release(dB); be->release(dC);
-    if (dS) be->release(dS);
-    if (dP) be->release(dP);
-  }
-}
-
-// Permute check: random 4-d index orders, scales, complex/real, beta; host loops.
 static int check_permute(Backend* be) {
   int fails = 0, runs = 0;
   srand(7);
@@ -205,82 +151,178 @@ static int check_permute(Backend* be) {
   return fails;
 }
 
-// Pair storage check: pack and unpack against host loops written from the
-// definition (lexicographic pairs, sign -1 per swapped pair), every flag combination.
+// Same-spin pair operations (SsOp) against host loops written from their definitions:
+// pairs i < j in lexicographic order, sign -1 per swapped pair, every mode and flag,
+// blocks of rows and columns that do and do not overlap, real and complex data.
 static int check_pairs(Backend* be) {
   int fails = 0, runs = 0;
   srand(11);
-  const int64_t dims[][2] = {{1, 5}, {2, 1}, {2, 3}, {5, 17}, {7, 40}, {36, 9}};
   auto pidx = [](int64_t i, int64_t j, int64_t n) {   // position of (i < j) among the pairs of n
     int64_t p = 0;
     for (int64_t a = 0; a < i; ++a) p += n - 1 - a;
     return p + (j - i - 1);
   };
+  const int64_t dims[][2] = {{2, 3}, {5, 4}, {7, 17}, {9, 40}};
+  // blocks (i0, ci, j0, cj) as fractions of n1: whole, rows, columns, overlapping, disjoint
   for (auto& d : dims)
-    for (int flags = 0; flags < 64; ++flags) {
-      const int64_t n1 = d[0], n2 = d[1];
-      const int pair2 = flags & 1, anti = (flags >> 1) & 1, mode = (flags >> 2) & 1, beta = (flags >> 3) & 1;
-      const bool cx = (flags >> 4) & 1;
-      const int64_t nblk = (flags >> 5) & 1 ? 2 : 1;
-      const int64_t rest = pair2 ? n2 * n2 : n2, np1 = n1 * (n1 - 1) / 2, nq = pair2 ? n2 * (n2 - 1) / 2 : n2;
-      const int64_t xbs = n1 * n1 * rest + 3, ybs = np1 * nq + 5;   // padded block strides
-      const int64_t nx = nblk * xbs, ny = nblk * ybs;
-      std::vector<double> x(2 * nx), y(2 * ny), xr, yr;
-      for (auto& v : x) v = rand() / (double)RAND_MAX - 0.5;
-      for (auto& v : y) v = rand() / (double)RAND_MAX - 0.5;
-      xr = x;
-      yr = y;
-      const double alpha = 0.625;
-      for (int64_t b = 0; b < nblk; ++b)
-        for (int64_t i = 0; i < n1; ++i)
-          for (int64_t j = 0; j < n1; ++j)
-            for (int64_t c = 0; c < rest; ++c) {
-              const int64_t a2 = pair2 ? c / n2 : 0, b2 = pair2 ? c % n2 : c;
-              const int64_t xo = b * xbs + (i * n1 + j) * rest + c;
-              for (int pl = 0; pl < (cx ? 2 : 1); ++pl) {
-                if (mode == 0) {
-                  if (i >= j || (pair2 && a2 >= b2)) continue;
-                  const int64_t yo = b * ybs + pidx(i, j, n1) * nq + (pair2 ? pidx(a2, b2, n2) : b2);
-                  const int64_t xs = b * xbs + (j * n1 + i) * rest + c;
-                  yr[pl * ny + yo] = alpha * (x[pl * nx + xo] - (anti ? x[pl * nx + xs] : 0.0));
-                } else {
-                  double v = beta ? x[pl * nx + xo] : 0.0;
-                  if (i != j && !(pair2 && a2 == b2)) {
-                    const int64_t q = pair2 ? pidx(std::min(a2, b2), std::max(a2, b2), n2) : b2;
-                    const double sg = (i < j ? 1.0 : -1.0) * (pair2 && b2 < a2 ? -1.0 : 1.0);
-                    v += alpha * sg * y[pl * ny + b * ybs + pidx(std::min(i, j), std::max(i, j), n1) * nq + q];
+    for (int mode = 0; mode <= 5; ++mode)
+      for (int variant = 0; variant < 16; ++variant) {
+        const int64_t n1 = d[0], n2 = d[1], np1 = n1 * (n1 - 1) / 2, np2 = n2 * (n2 - 1) / 2;
+        const bool cx = variant & 1;
+        const int anti1 = (variant >> 1) & 1, anti2 = (variant >> 2) & 1, beta = (variant >> 3) & 1;
+        int64_t i0 = 0, ci = n1, j0 = 0, cj = n1;
+        const int blk = variant % 5;
+        if (blk == 1) { i0 = n1 / 3; ci = n1 - n1 / 3 - (n1 > 2 ? 1 : 0); }
+        if (blk == 2) { j0 = n1 / 2; cj = n1 - n1 / 2; }
+        if (blk == 3) { i0 = 0; ci = (n1 + 1) / 2; j0 = n1 / 3; cj = n1 - n1 / 3; }
+        if (blk == 4) { i0 = n1 / 2; ci = n1 - n1 / 2; j0 = 0; cj = n1 / 2 > 0 ? n1 / 2 : 1; }
+        SsOp op;
+        op.mode = mode; op.n1 = n1; op.n2 = n2; op.anti1 = anti1; op.anti2 = anti2; op.beta = beta;
+        op.alpha = 0.625;
+        int64_t nx = 0, ny = np1 * np2;
+        if (mode == SsOp::kExpand || mode == SsOp::kAccum) { op.i0 = i0; op.ci = ci; op.j0 = j0; op.cj = cj; nx = ci * cj * n2 * n2; }
+        if (mode == SsOp::kAccumRows) { op.i0 = np1 / 4; op.ci = np1 - np1 / 4; nx = op.ci * n2 * n2; }
+        if (mode == SsOp::kT1T1) nx = n1 * n2;   // the t1 operand
+        if (mode == SsOp::kMask) nx = n1 + n2;   // the two mask vectors
+        int64_t pack_rows = 0;
+        if (mode == SsOp::kPackSlab) {
+          op.pair2 = variant & 2 ? 1 : 0;
+          const int64_t rest = op.pair2 ? n2 * n2 : n2;
+          op.i0 = n1 / 4; op.ci = n1 - n1 / 4 - (n1 > 3 ? 1 : 0);
+          nx = op.ci * n1 * rest;
+          int64_t e_end = op.i0 + op.ci;
+          pack_rows = 0;
+          for (int64_t e = op.i0; e < e_end; ++e) pack_rows += n1 - 1 - e;
+          ny = pack_rows * (op.pair2 ? np2 : n2);
+        }
+        if (mode == SsOp::kT1T1 && !cx) continue;   // complex only
+        const int npl = cx ? 2 : 1;
+        std::vector<double> x(2 * nx + 1), y(2 * ny + 1);
+        for (auto& v : x) v = rand() / (double)RAND_MAX - 0.5;
+        for (auto& v : y) v = rand() / (double)RAND_MAX - 0.5;
+        if (mode == SsOp::kMask)
+          for (int64_t k = 0; k < nx; ++k) x[k] = (rand() % 3) ? 1.0 : 0.0;
+        std::vector<double> xr = x, yr = y;
+        auto X = [&](int pl, int64_t o) { return x[pl * nx + o]; };
+        auto Y = [&](int pl, int64_t o) { return y[pl * ny + o]; };
+        switch (mode) {
+          case SsOp::kExpand:
+            for (int64_t ii = 0; ii < ci; ++ii)
+              for (int64_t jj = 0; jj < cj; ++jj)
+                for (int64_t a = 0; a < n2; ++a)
+                  for (int64_t b = 0; b < n2; ++b)
+                    for (int pl = 0; pl < npl; ++pl) {
+                      const int64_t i = i0 + ii, j = j0 + jj, o = ((ii * cj + jj) * n2 + a) * n2 + b;
+                      double v = 0.0;
+                      if (i != j && a != b)
+                        v = op.alpha * (i < j ? 1 : -1) * (a < b ? 1 : -1) *
+                            Y(pl, pidx(std::min(i, j), std::max(i, j), n1) * np2 + pidx(std::min(a, b), std::max(a, b), n2));
+                      xr[pl * nx + o] = v + (beta ? X(pl, o) : 0.0);
+                    }
+            break;
+          case SsOp::kAccum: {
+            auto inI = [&](int64_t k) { return k >= i0 && k < i0 + ci; };
+            auto inJ = [&](int64_t k) { return k >= j0 && k < j0 + cj; };
+            auto xv = [&](int pl, int64_t i, int64_t j, int64_t a, int64_t b) {
+              return X(pl, (((i - i0) * cj + (j - j0)) * n2 + a) * n2 + b);
+            };
+            for (int64_t k = 0; k < n1; ++k)
+              for (int64_t l = k + 1; l < n1; ++l)
+                for (int64_t a = 0; a < n2; ++a)
+                  for (int64_t b = a + 1; b < n2; ++b)
+                    for (int pl = 0; pl < npl; ++pl) {
+                      double v = 0.0;
+                      if (inI(k) && inJ(l)) v += xv(pl, k, l, a, b) - (anti2 ? xv(pl, k, l, b, a) : 0.0);
+                      if (anti1 && inI(l) && inJ(k)) v -= xv(pl, l, k, a, b) - (anti2 ? xv(pl, l, k, b, a) : 0.0);
+                      yr[pl * ny + pidx(k, l, n1) * np2 + pidx(a, b, n2)] += op.alpha * v;
+                    }
+            break;
+          }
+          case SsOp::kAccumRows:
+            for (int64_t pp = 0; pp < op.ci; ++pp)
+              for (int64_t a = 0; a < n2; ++a)
+                for (int64_t b = a + 1; b < n2; ++b)
+                  for (int pl = 0; pl < npl; ++pl)
+                    yr[pl * ny + (op.i0 + pp) * np2 + pidx(a, b, n2)] +=
+                        op.alpha * (X(pl, (pp * n2 + a) * n2 + b) - (anti2 ? X(pl, (pp * n2 + b) * n2 + a) : 0.0));
+            break;
+          case SsOp::kT1T1:
+            for (int64_t i = 0; i < n1; ++i)
+              for (int64_t j = i + 1; j < n1; ++j)
+                for (int64_t a = 0; a < n2; ++a)
+                  for (int64_t b = a + 1; b < n2; ++b) {
+                    auto ur = [&](int64_t p, int64_t q) { return X(0, p * n2 + q); };
+                    auto ui = [&](int64_t p, int64_t q) { return X(1, p * n2 + q); };
+                    const double vr = ur(i, a) * ur(j, b) - ui(i, a) * ui(j, b) - (ur(i, b) * ur(j, a) - ui(i, b) * ui(j, a));
+                    const double vi = ur(i, a) * ui(j, b) + ui(i, a) * ur(j, b) - (ur(i, b) * ui(j, a) + ui(i, b) * ur(j, a));
+                    const int64_t o = pidx(i, j, n1) * np2 + pidx(a, b, n2);
+                    yr[o] = op.alpha * vr + (beta ? Y(0, o) : 0.0);
+                    yr[ny + o] = op.alpha * vi + (beta ? Y(1, o) : 0.0);
                   }
-                  xr[pl * nx + xo] = v;
+            break;
+          case SsOp::kMask:
+            for (int64_t i = 0; i < n1; ++i)
+              for (int64_t j = i + 1; j < n1; ++j)
+                for (int64_t a = 0; a < n2; ++a)
+                  for (int64_t b = a + 1; b < n2; ++b)
+                    for (int pl = 0; pl < npl; ++pl) {
+                      const int64_t o = pidx(i, j, n1) * np2 + pidx(a, b, n2);
+                      yr[pl * ny + o] = Y(pl, o) * x[i] * x[j] * x[n1 + a] * x[n1 + b];
+                    }
+            break;
+          default: {   // kPackSlab
+            const int64_t base = pidx(op.i0, op.i0 + 1, n1), rest = op.pair2 ? n2 * n2 : n2, nq = op.pair2 ? np2 : n2;
+            for (int64_t ee = 0; ee < op.ci; ++ee)
+              for (int64_t f = op.i0 + ee + 1; f < n1; ++f)
+                for (int pl = 0; pl < npl; ++pl) {
+                  const int64_t p = pidx(op.i0 + ee, f, n1) - base, xo = (ee * n1 + f) * rest;
+                  if (op.pair2) {
+                    for (int64_t a = 0; a < n2; ++a)
+                      for (int64_t b = a + 1; b < n2; ++b)
+                        yr[pl * ny + p * nq + pidx(a, b, n2)] = op.alpha * (X(pl, xo + a * n2 + b) - X(pl, xo + b * n2 + a));
+                  } else {
+                    for (int64_t c = 0; c < n2; ++c) yr[pl * ny + p * nq + c] = op.alpha * X(pl, xo + c);
+                  }
                 }
-              }
-            }
-      double* dx = (double*)be->alloc(16 * nx + 8);
-      double* dy = (double*)be->alloc(16 * ny + 8);
-      be->h2d(dx, x.data(), 16 * nx);
-      be->h2d(dy, y.data(), 16 * ny);
-      PairOp op;
-      op.n1 = n1; op.n2 = n2; op.nblk = nblk; op.pair2 = pair2; op.anti = anti; op.mode = mode; op.beta = beta;
-      op.alpha = alpha;
-      op.x_re = dx; op.x_im = cx ? dx + nx : nullptr; op.x_bs = xbs;
-      op.y_re = dy; op.y_im = cx ? dy + ny : nullptr; op.y_bs = ybs;
-      be->pairs(op);
-      be->sync();
-      std::vector<double> xo(2 * nx), yo(2 * ny);
-      be->d2h(xo.data(), dx, 16 * nx);
-      be->d2h(yo.data(), dy, 16 * ny);
-      double e = 0.0;
-      for (int64_t k = 0; k < 2 * nx; ++k) e = std::fmax(e, std::fabs(xo[k] - xr[k]));
-      for (int64_t k = 0; k < 2 * ny; ++k) e = std::fmax(e, std::fabs(yo[k] - yr[k]));
-      std::string m;
-      const bool ok = e <= 1e-15 && be->ok(&m);
-      ++runs;
-      if (!ok) {
-        ++fails;
-        printf("PAIRS FAIL n1 %ld n2 %ld flags %d err %.3g %s\n", (long)n1, (long)n2, flags, e, m.c_str());
+          }
+        }
+        double* dx = (double*)be->alloc(16 * nx + 16);
+        double* dy = (double*)be->alloc(16 * ny + 16);
+        be->h2d(dx, x.data(), 8 * x.size());
+        be->h2d(dy, y.data(), 8 * y.size());
+        // pair tables
+        std::vector<int32_t> t(2 * np1 + 2 * np2 + 1);
+        int64_t k = 0;
+        for (int i = 0; i < n1; ++i) for (int j = i + 1; j < n1; ++j) { t[k] = i; t[np1 + k] = j; ++k; }
+        k = 0;
+        for (int a = 0; a < n2; ++a) for (int b = a + 1; b < n2; ++b) { t[2 * np1 + k] = a; t[2 * np1 + np2 + k] = b; ++k; }
+        int32_t* dt = (int32_t*)be->alloc(4 * t.size());
+        be->h2d(dt, t.data(), 4 * t.size());
+        op.pt.oi = dt; op.pt.oj = dt + np1; op.pt.va = dt + 2 * np1; op.pt.vb = dt + 2 * np1 + np2;
+        op.y_re = dy; op.y_im = cx ? dy + ny : nullptr;
+        if (mode == SsOp::kT1T1) { op.u_re = dx; op.u_im = dx + nx; }
+        else if (mode == SsOp::kMask) { op.m1 = dx; op.m2 = dx + n1; }
+        else { op.x_re = dx; op.x_im = cx ? dx + nx : nullptr; }
+        be->ss(op);
+        be->sync();
+        std::vector<double> xo(x.size()), yo(y.size());
+        be->d2h(xo.data(), dx, 8 * x.size());
+        be->d2h(yo.data(), dy, 8 * y.size());
+        double e = 0.0;
+        for (int64_t q = 0; q < npl * nx; ++q) e = std::fmax(e, std::fabs(xo[q] - xr[q]));
+        for (int64_t q = 0; q < npl * ny; ++q) e = std::fmax(e, std::fabs(yo[q] - yr[q]));
+        std::string m;
+        const bool ok = e <= 1e-14 && be->ok(&m);
+        ++runs;
+        if (!ok) {
+          ++fails;
+          printf("PAIRS FAIL mode %d n1 %ld n2 %ld variant %d err %.3g %s\n", mode, (long)n1, (long)n2, variant, e,
+                 m.c_str());
+        }
+        be->release(dx);
+        be->release(dy);
+        be->release(dt);
       }
-      be->release(dx);
-      be->release(dy);
-    }
   printf("pairs probe: %d runs, %d failures\n", runs, fails);
   return fails;
 }
@@ -289,11 +331,6 @@ int main(int argc, char** argv) {
   std::string err;
   Backend* be = make_hip_backend(nullptr, &err);
   if (!be) { printf("no backend %s\n", err.c_str()); return 1; }
-  if (argc > 1 && std::string(argv[1]) == "bench") {   // bench [lowest precision [highest precision]]
-    const int lo = argc > 2 ? atoi(argv[2]) : 0;
-    bench(be, lo, argc > 3 ? atoi(argv[3]) : (argc > 2 ? lo : 2));
-    return 0;
-  }
   const int f = check_permute(be) + check_pairs(be);
   return (check(be) || f) ? 2 : 0;
 }

@@ -114,6 +114,10 @@ typedef struct {
   int32_t plan_block;      /* 0: automatic; > 0: occupied indices per block of the ring
                               intermediates and of the expanded same-spin rows.  With either
                               set, the plan is used as given (OOM if it does not fit). */
+  int32_t progress;        /* 1: a residual evaluation that runs in blocks waits for the
+                              stream after each ring block and integral slab and writes one
+                              line per block to stderr (elapsed seconds): long evaluations
+                              report where they are */
 } rteom_options;
 
 /* Fill *opt with defaults: FP64, plain map, tolerance 1e-10, 50 passes,
@@ -213,8 +217,20 @@ rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_
                         int32_t* vir_list);
 
 /* Replace the current amplitudes (host layout above).  Entries of non-existent spin
-   amplitudes are ignored (set to zero).  Test and benchmark hook. */
+   amplitudes are ignored (set to zero).  t1 = t2 = NULL: the amplitudes have been
+   written in place into the device set that rteom_device_sets returns; they are taken
+   as they are (masked like host input).  Either way E(T_n) is recomputed and a failed
+   state is cleared.  Test and benchmark hook. */
 rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double* t2);
+
+/* Device addresses of the current amplitude set (x) and of the residual set (r, written by
+   rteom_residual), each *doubles doubles in the device layout (planar: the real parts of
+   t1, same-spin pairs, alpha-beta block, then the imaginary parts in the same order).
+   They lie in the context's workspace and stay valid until rteom_free.  For callers that
+   cannot afford host copies at large sizes: write x in place, then call
+   rteom_set_amplitudes(ctx, NULL, NULL); read r after rteom_residual(ctx, NULL, NULL).
+   Work on them must be ordered with the context's stream.  Test and benchmark hook. */
+rteom_status rteom_device_sets(const rteom_ctx* ctx, void** x, void** r, int64_t* doubles);
 
 /* Copy the current amplitudes to host (layout above). */
 rteom_status rteom_get_amplitudes(const rteom_ctx* ctx, double* t1, double* t2);

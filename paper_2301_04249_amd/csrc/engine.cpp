@@ -3,6 +3,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 
 namespace rteom {
@@ -283,18 +284,36 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
     cl = order;
   }
   // Inputs: copy to [batch][rows][sum] / [batch][sum][cols] when not flat.
+  // The product kernels address 16 rows of k and 128 rows or columns of one operand
+  // through one buffer resource of at most 2 GiB: an operand whose tile would span
+  // more is copied with the sum index contiguous.
+  auto window_ok = [](int64_t s_mn, int64_t s_k) {
+    return (127 * std::llabs(s_mn) + 15 * std::llabs(s_k) + 1) * 8 < (int64_t(1) << 31);
+  };
   auto prep = [&](const View& X, const std::string& xl, const std::string& g0,
-                  const std::string& g1, const std::string& g2, std::string* out_l) -> View {
+                  const std::string& g1, const std::string& g2, bool is_b, std::string* out_l) -> View {
     // batch letters missing from this operand are broadcast (stride 0)
     std::string gb;
     for (char c : g0)
       if (pos(xl, c) >= 0) gb += c;
+    const std::string& gk = is_b ? g1 : g2;
+    const std::string& gmn = is_b ? g2 : g1;
     int64_t t0, t1, t2;
     if (flat(X, xl, gb, &t0) && flat(X, xl, g1, &t1) && flat(X, xl, g2, &t2)) {
-      *out_l = xl;
-      return X;
+      int64_t sk = 0, smn = 0;
+      flat(X, xl, gk, &sk);
+      flat(X, xl, gmn, &smn);
+      if (window_ok(smn, sk)) {
+        *out_l = xl;
+        return X;
+      }
     }
     std::string order = gb + g1 + g2;
+    if (is_b) {
+      int64_t nn = 1;
+      for (char c : g2) nn *= dim_of(c);
+      if (!window_ok(1, nn)) order = gb + g2 + g1;   // [batch][cols][sum]
+    }
     View t;
     t.nd = static_cast<int>(order.size());
     int64_t n = 1;
@@ -320,8 +339,8 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
     return t;
   };
   std::string al, bl;
-  View Au = prep(A, sp.a, Bg, Mg, Kg, &al);
-  View Bu = prep(B, sp.b, Bg, Kg, Ng, &bl);
+  View Au = prep(A, sp.a, Bg, Mg, Kg, false, &al);
+  View Bu = prep(B, sp.b, Bg, Kg, Ng, true, &bl);
 
   GemmOp op;
   op.M = 1;

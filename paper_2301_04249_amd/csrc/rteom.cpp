@@ -29,8 +29,10 @@
 //   amplitude-sized buffers (iterate X, rhs, residual R) as in Table 2's three
 //   timeline tensors.  C(t) accumulates i E(T) with the same trapezoid weights.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <complex>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -203,6 +205,17 @@ struct Context {
     return with_frac(x, {f_o[s], f_o[s], f_v[s], f_v[s]});
   }
 
+  // Progress report of a long residual evaluation (rteom_options.progress): waits for the
+  // stream, then one line to stderr.
+  std::chrono::steady_clock::time_point t_res;
+  void progress(const char* what, int64_t k, int64_t n) {
+    if (dry || !opt.progress) return;
+    be->sync();
+    const double s = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_res).count();
+    std::fprintf(stderr, "[rteom] residual: %s %lld/%lld done (%.1f s)\n", what, (long long)k, (long long)n, s);
+    std::fflush(stderr);
+  }
+
   double* take(int64_t n) { return arena.take(n); }
   void h2d(double* dst, const double* src, int64_t n) {
     if (!dry) be->h2d(dst, src, n * sizeof(double));
@@ -257,19 +270,42 @@ struct Context {
   // [ce][nv][no][nv] and (me|bf) - (mf|be) rows [pairs (e<f), e in slab][m][b] for the
   // virtual indices e0 .. e0+ce-1 (Sec. 2.3: (pq|rs) = sum_Q L^Q_pq L^Q_rs), in the
   // engine's current precision.
-  void build_slab(int64_t e0, int64_t ce, const View& Vs, double* Wdst, const View& Bs, double* Bpdst) {
+  // Cholesky vectors with the vector index Q innermost, the operand layout of the slab
+  // products (both operands then stream along their sum index): Lt_vv[p][q][Q] over
+  // virtual p, q and Lt_vo[e][m][Q] = L^Q_me.
+  struct SlabOperands {
+    View vv, vo;
+  };
+  SlabOperands slab_operands() {
+    SlabOperands o;
+    o.vv = eng.temp({nv, nv, nq}, false);
+    o.vo = eng.temp({nv, no, nq}, false);
+    eng.add(o.vv, reorder(Lv(Lvv, nv, nv), {1, 2, 0}), 1.0, 0.0, 0);
+    eng.add(o.vo, reorder(Lv(Lov, no, nv), {2, 1, 0}), 1.0, 0.0, 0);
+    return o;
+  }
+
+  void build_slab(const SlabOperands& L, int64_t e0, int64_t ce, const View& Vs, double* Wdst, const View& Bs,
+                  double* Bpdst) {
     const int64_t Q = nq;
     {
       // the product lands in a GEMM-order temporary before it is permuted into
       // place: sub-slabs of e bound that temporary to kSlabDoubles
       const int64_t per_e = std::max<int64_t>(1, (int64_t)nv * nv * nv);
       const int64_t sub = std::max<int64_t>(1, std::min<int64_t>(ce, kSlabDoubles / per_e));
+      // (ae|bf) = sum_Q L^Q_ae L^Q_bf
       for (int64_t k = 0; k < ce; k += sub) {
         const int64_t m = std::min<int64_t>(sub, ce - k);
-        View Le = block(Lv(Lvv, nv, nv), {0, 0, e0 + k}, {Q, nv, m});
-        View Lm = block(Lv(Lov, no, nv), {0, 0, e0 + k}, {Q, no, m});
-        eng.contract("Qae,Qbf->efab", Le, Lv(Lvv, nv, nv), block(Vs, {k, 0, 0, 0}, {m, nv, nv, nv}), 1.0, 0);
-        eng.contract("Qme,Qbf->efmb", Lm, Lv(Lvv, nv, nv), block(Bs, {k, 0, 0, 0}, {m, nv, no, nv}), 1.0, 0);
+        eng.contract("eaQ,fbQ->efab", block(L.vv, {e0 + k, 0, 0}, {m, nv, Q}), L.vv,
+                     block(Vs, {k, 0, 0, 0}, {m, nv, nv, nv}), 1.0, 0);
+      }
+      // (me|bf) = sum_Q L^Q_me L^Q_bf
+      const int64_t per_b = std::max<int64_t>(1, (int64_t)nv * no * nv);
+      const int64_t sub_b = std::max<int64_t>(1, std::min<int64_t>(ce, kSlabDoubles / per_b));
+      for (int64_t k = 0; k < ce; k += sub_b) {
+        const int64_t m = std::min<int64_t>(sub_b, ce - k);
+        eng.contract("emQ,fbQ->efmb", block(L.vo, {e0 + k, 0, 0}, {m, no, Q}), L.vv,
+                     block(Bs, {k, 0, 0, 0}, {m, nv, no, nv}), 1.0, 0);
       }
     }
     SsOp w;
@@ -281,7 +317,7 @@ struct Context {
     View Xs = eng.temp({ce, nv, no, nv}, false);
     eng.add(Xs, Bs, 1.0, 0.0, 0);
     // (mf|be) for e in the slab: sum_Q L^Q_mf L^Q_be
-    eng.contract("Qmf,Qbe->efmb", Lv(Lov, no, nv), block(Lv(Lvv, nv, nv), {0, 0, e0}, {Q, nv, ce}), Xs, -1.0, 1);
+    eng.contract("fmQ,ebQ->efmb", L.vo, block(L.vv, {e0, 0, 0}, {ce, nv, Q}), Xs, -1.0, 1);
     SsOp z;
     z.mode = SsOp::kPackSlab;
     z.n1 = nv; z.n2 = (int64_t)no * nv; z.pair2 = 0; z.i0 = e0; z.ci = ce;
@@ -474,11 +510,14 @@ struct Context {
       View Vv = make_view(Vlad, nullptr, {nv, nv, nv, nv});
       View Bv = make_view(B1, nullptr, {nv, nv, no, nv});
       const int64_t ce = std::max<int64_t>(1, std::min<int64_t>(nv, kSlabDoubles / std::max<int64_t>(1, (int64_t)nv * nv * nv)));
+      const size_t ml = arena.mark();
+      const SlabOperands L = slab_operands();
       for (int64_t e0 = 0; e0 < nv; e0 += ce) {
         const int64_t m = std::min<int64_t>(ce, nv - e0);
-        build_slab(e0, m, block(Vv, {e0, 0, 0, 0}, {m, nv, nv, nv}), Wpp + pair_start(e0, nv) * npv(),
+        build_slab(L, e0, m, block(Vv, {e0, 0, 0, 0}, {m, nv, nv, nv}), Wpp + pair_start(e0, nv) * npv(),
                    block(Bv, {e0, 0, 0, 0}, {m, nv, no, nv}), B1p + pair_start(e0, nv) * no * nv);
       }
+      arena.release(ml);
     }
     // T(0) = 0, C(0) = 0
     if (!dry) {
@@ -542,6 +581,7 @@ struct Context {
     eng.flops = eng.alg_flops = 0.0;
     for (int k = 0; k < kNumPhases; ++k) eng.phase_flops[k] = eng.alg_phase_flops[k] = 0.0;
     eng.set_phase(kPhaseGemm);
+    t_res = std::chrono::steady_clock::now();
     fill(Rs, 2 * lay.size());        // every term below accumulates
     const int64_t nov = (int64_t)no * nv;
     const int64_t ci = std::max<int64_t>(1, std::min<int64_t>(plan.ci, no));
@@ -696,6 +736,7 @@ struct Context {
         arena.release(mr);
       }
       arena.release(mw);
+      if (cj < no) progress("ring block", std::min<int64_t>(j0 + cj, no), no);
     }
     eng.set_phase(kPhaseGemm);
     arena.release(mk_vv);
@@ -710,6 +751,9 @@ struct Context {
                     make_view(B1, nullptr, {nv, nv, no, nv}), B1p, Z3ab, Zp, Z2ab, true);
     } else {
       const int64_t es = std::max<int64_t>(1, std::min<int64_t>(plan.es, nv));
+      eng.set_phase(kPhaseBuild);
+      const SlabOperands L = slab_operands();
+      eng.set_phase(kPhaseGemm);
       for (int64_t e0 = 0; e0 < nv; e0 += es) {
         const int64_t ce = std::min<int64_t>(es, nv - e0);
         const int64_t nr = pair_start(e0 + ce, nv) - pair_start(e0, nv);
@@ -719,10 +763,11 @@ struct Context {
         View Vs = eng.temp({ce, nv, nv, nv}, false);
         View Bs = eng.temp({ce, nv, no, nv}, false);
         eng.set_phase(kPhaseBuild);
-        build_slab(e0, ce, Vs, Wsl, Bs, Bpsl);
+        build_slab(L, e0, ce, Vs, Wsl, Bs, Bpsl);
         eng.set_phase(kPhaseGemm);
         slab_products(Xs, Rs, e0, ce, Vs, Wsl, Bs, Bpsl, Z3ab, Zp, Z2ab, e0 == 0);
         arena.release(ms);
+        if ((e0 / es) % 8 == 7 || e0 + ce >= nv) progress("integral slab", e0 + ce, nv);
       }
     }
     // same-spin doubles: the terms in full storage over blocks of rows, the hole
@@ -1537,16 +1582,27 @@ rteom_status rteom_set_amplitudes(rteom_ctx* ctx, const double* t1, const double
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
   Context& c = ctx->c;
   return guarded(ctx, [&] {
-    std::vector<double> buf;
-    to_planar(c, t1, t2, buf);
-    for (double v : buf)
-      if (!std::isfinite(v)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitude");
-    c.be->h2d(c.X, buf.data(), buf.size() * sizeof(double));
+    if (t1 || t2) {
+      std::vector<double> buf;
+      to_planar(c, t1, t2, buf);
+      for (double v : buf)
+        if (!std::isfinite(v)) throw Error(RTEOM_ERR_NONFINITE, "non-finite amplitude");
+      c.be->h2d(c.X, buf.data(), buf.size() * sizeof(double));
+    }
     c.mask_set(c.X);
     c.energy(c.X, c.e_hist + 2 * c.nsteps);   // E(T_n) for the next trapezoid
     c.be->fill(c.dbad, 1, 0.0);
     c.failed = false;
   });
+}
+
+rteom_status rteom_device_sets(const rteom_ctx* cctx, void** x, void** r, int64_t* doubles) {
+  if (!cctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  const Context& c = cctx->c;
+  if (x) *x = c.X;
+  if (r) *r = c.R;
+  if (doubles) *doubles = 2 * c.lay.size();
+  return RTEOM_OK;
 }
 
 rteom_status rteom_get_amplitudes(const rteom_ctx* cctx, double* t1, double* t2) {

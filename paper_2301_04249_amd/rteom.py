@@ -23,7 +23,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
     "rteom_spectral", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
-    "rteom_residual_flops", "rteom_plan_info", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
+    "rteom_residual_flops", "rteom_plan_info", "rteom_device_sets", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
     "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
@@ -55,6 +55,7 @@ class Options(ctypes.Structure):
         ("mem_limit", ctypes.c_size_t),
         ("plan_slab", ctypes.c_int32),
         ("plan_block", ctypes.c_int32),
+        ("progress", ctypes.c_int32),
     ]
 
 
@@ -96,6 +97,8 @@ def load(path: str = LIB_PATH):
     lib.rteom_residual.argtypes = [c.c_void_p, _dp, _dp]
     lib.rteom_energy.argtypes = [c.c_void_p, _dp]
     lib.rteom_residual_flops.argtypes = [c.c_void_p, _dp]
+    lib.rteom_device_sets.argtypes = [c.c_void_p, c.POINTER(c.c_void_p), c.POINTER(c.c_void_p),
+                                      c.POINTER(c.c_int64)]
     lib.rteom_plan_info.argtypes = [c.c_void_p, _ip, c.POINTER(c.c_int64), c.POINTER(c.c_int64),
                                     c.POINTER(c.c_int64), _dp, c.POINTER(c.c_size_t)]
     lib.rteom_profile.argtypes = [c.c_void_p, c.c_uint32]
@@ -150,7 +153,8 @@ class Propagator:
 
     def __init__(self, eps, chol, n_occ_a, n_occ_b, core_orb=0, core_spin=1, prec="fp64", fp_map=0,
                  fixed_iters=0, max_iter=50, tol=1e-10, include_ft1=True, max_steps=100000,
-                 stream=None, workspace=None, graph=False, tune=True, anderson=0, mem_limit=0, plan_slab=0, plan_block=0, lib_path=LIB_PATH):
+                 stream=None, workspace=None, graph=False, tune=True, anderson=0, mem_limit=0, plan_slab=0, plan_block=0, progress=False,
+                 lib_path=LIB_PATH):
         self.lib = load(lib_path)
         eps = np.ascontiguousarray(eps, dtype=np.float64)
         chol = np.ascontiguousarray(chol, dtype=np.float64)
@@ -171,6 +175,7 @@ class Propagator:
         opt.mem_limit = int(mem_limit)
         opt.plan_slab = int(plan_slab)
         opt.plan_block = int(plan_block)
+        opt.progress = 1 if progress else 0
         opt.stream = stream
         self._ws = None
         if workspace == "torch":
@@ -238,6 +243,26 @@ class Propagator:
         if not full:
             return tss, tab
         return np.stack([expand_same_spin(tss[0], no, nv), tab, expand_same_spin(tss[1], no, nv)])
+
+    def device_sets(self):
+        """(x, r): float64 torch views of the device amplitude set and residual set inside the
+        torch workspace (rteom_device_sets; workspace="torch" only), planar device layout."""
+        x, r, n = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_int64()
+        st = self.lib.rteom_device_sets(self.h, ctypes.byref(x), ctypes.byref(r), ctypes.byref(n))
+        self._check(st, self.h)
+        if self._ws is None:
+            raise RteomError(1, "device_sets needs workspace='torch'")
+        base = self._ws.data_ptr()
+        views = []
+        for p in (x.value, r.value):
+            off = p - base
+            views.append(self._ws[off: off + 8 * n.value].view(__import__("torch").float64))
+        return views[0], views[1]
+
+    def amplitudes_written(self):
+        """The device amplitude set was written in place: mask it and recompute E(T_n)."""
+        st = self.lib.rteom_set_amplitudes(self.h, None, None)
+        self._check(st, self.h)
 
     def plan(self):
         """The memory plan rteom_init chose (rteom_plan_info)."""

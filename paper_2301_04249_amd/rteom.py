@@ -178,16 +178,18 @@ class Propagator:
         opt.progress = 1 if progress else 0
         opt.stream = stream
         self._ws = None
-        if workspace == "torch":
+        if workspace in ("torch", "torch-cpu"):
+            # "torch-cpu": host memory, for the library's host test build only
             import torch
             need = ctypes.c_size_t(0)
             st = self.lib.rteom_workspace_query(n, n_occ_a, n_occ_b, nq, core_orb, core_spin, ctypes.byref(opt),
                                                 ctypes.byref(need))
             self._check(st, None)
-            self._ws = torch.empty(int(need.value), dtype=torch.uint8, device="cuda")
+            self._ws = torch.empty(int(need.value), dtype=torch.uint8,
+                                   device="cuda" if workspace == "torch" else "cpu")
             opt.workspace = self._ws.data_ptr()
             opt.workspace_bytes = int(need.value)
-            if stream is None:
+            if stream is None and workspace == "torch":
                 if graph:   # a stream of its own (at the default priority) so that it can be captured
                     self._stream = torch.cuda.Stream()
                     opt.stream = self._stream.cuda_stream

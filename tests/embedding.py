@@ -106,3 +106,127 @@ def check(P, emb, prec, tol):
     es = emb["e_s"]
     print(f"E_S: library {e_full - e_p:.14e}, oracle {es:.14e}", flush=True)
     assert abs((e_full - e_p) - es) <= 1e-11 * max(abs(es), abs(e_full))
+
+
+def pidx(i, j, n):
+    """Position of the pair i < j among the pairs of n (the library's lexicographic order)."""
+    return i * (2 * n - i - 1) // 2 + j - i - 1
+
+
+def check_device(P, emb, tol, run):
+    """The same properties at sizes where host copies of the amplitudes would not fit: the
+    amplitudes are written in place into the device set (rteom_device_sets), the residual is
+    read where the library leaves it, and every comparison runs on the device.  `run` wraps
+    the residual evaluation (e.g. to let its progress lines through).  Returns the errors."""
+    import torch
+    no, nv = P.no, P.nv
+    occ, vir = np.array(P.occ_list), np.array(P.vir_list)
+    os_, vs_ = emb["in_s"][occ], emb["in_s"][vir]
+    ks, vs = int(os_.sum()), int(vs_.sum())
+    assert os_[:ks].all() and vs_[:vs].all()      # S leads both lists (orbital 0 heads V)
+    rank = np.cumsum(emb["in_s"]) - 1
+    small = emb["small"]
+    b1s, b2s = blocks.to_blocks(small, rank[occ[:ks]], rank[vir[:vs]], *emb["t"])
+    e1, e2 = blocks.to_blocks(small, rank[occ[:ks]], rank[vir[:vs]], *emb["r"])
+    npo, npv, n1 = no * (no - 1) // 2, nv * (nv - 1) // 2, no * nv
+    nss, nab = npo * npv, no * no * nv * nv
+    size = 2 * n1 + 2 * nss + nab
+    x, r = P.device_sets()
+    assert x.numel() == 2 * size
+    dev = x.device
+
+    def parts(buf, plane):
+        b = buf[plane * size:(plane + 1) * size]
+        return (b[:2 * n1].view(2, no, nv), b[2 * n1:2 * n1 + 2 * nss].view(2, npo, npv),
+                b[2 * n1 + 2 * nss:].view(no, no, nv, nv))
+
+    ij_s = [(i, j) for i in range(ks) for j in range(i + 1, ks)]
+    ab_s = [(a, b) for a in range(vs) for b in range(a + 1, vs)]
+    ps = torch.tensor([pidx(i, j, no) for i, j in ij_s], device=dev, dtype=torch.long)
+    qs = torch.tensor([pidx(a, b, nv) for a, b in ab_s], device=dev, dtype=torch.long)
+    p0, q0 = pidx(ks, ks + 1, no), pidx(vs, vs + 1, nv)     # first pair with both indices in S'
+    pm = torch.tensor([pidx(i, j, no) for i in range(ks) for j in range(ks, no)], device=dev, dtype=torch.long)
+    qm = torch.tensor([pidx(a, b, nv) for a in range(vs) for b in range(vs, nv)], device=dev, dtype=torch.long)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(77)
+
+    def randn(*shape):
+        return torch.randn(shape, generator=gen, device=dev, dtype=torch.float64) * 1e-3
+
+    def write(with_s):
+        x.zero_()
+        for plane, part in ((0, np.real), (1, np.imag)):
+            t1v, tssv, tabv = parts(x, plane)
+            if with_s:
+                t1v[:, :ks, :vs] = torch.from_numpy(np.ascontiguousarray(part(b1s))).to(dev)
+                tabv[:ks, :ks, :vs, :vs] = torch.from_numpy(np.ascontiguousarray(part(b2s[1]))).to(dev)
+                for s, blk in ((0, 0), (1, 2)):
+                    vals = np.array([[part(b2s[blk][i, j, a, b]) for a, b in ab_s] for i, j in ij_s])
+                    tssv[s][ps[:, None], qs[None, :]] = torch.from_numpy(vals).to(dev)
+            t1v[:, ks:, vs:] = randn(2, no - ks, nv - vs)
+            for i in range(ks, no):
+                tabv[i, ks:, vs:, vs:] = randn(no - ks, nv - vs, nv - vs)
+            for s in range(2):
+                for p in range(p0, npo, 128):
+                    m = min(128, npo - p)
+                    tssv[s][p:p + m, q0:] = randn(m, npv - q0)
+        P.amplitudes_written()
+
+    write(True)
+    e_full = P.energy()
+    run(lambda: P.residual(want=False))
+    if x.is_cuda:
+        torch.cuda.synchronize()
+
+    def cplx(fn):
+        re, im = fn(parts(r, 0)), fn(parts(r, 1))
+        return re.cpu().numpy() + 1j * im.cpu().numpy()
+
+    g1 = cplx(lambda t: t[0][:, :ks, :vs])
+    gab = cplx(lambda t: t[2][:ks, :ks, :vs, :vs])
+    gss = [cplx(lambda t, s=s: t[1][s][ps][:, qs]) for s in range(2)]
+    ess = [np.array([[e2[blk][i, j, a, b] for a, b in ab_s] for i, j in ij_s]) for blk in (0, 2)]
+    scale = max(np.abs(e1).max(), np.abs(e2).max())
+    err = max(np.abs(g1 - e1).max(), np.abs(gab - e2[1]).max(),
+              max(np.abs(g - e).max() for g, e in zip(gss, ess))) / scale
+    print(f"S block: max |R - R_oracle| / max |R_oracle| = {err:.3e}", flush=True)
+
+    # every element joining S and S' vanishes (largest |Re|, |Im| on the device)
+    def amax(t):
+        if t.numel() == 0:
+            return 0.0
+        if t.numel() <= (1 << 26) or t.shape[0] == 1:
+            return float(t.abs().max())
+        step = max(1, t.shape[0] * (1 << 26) // t.numel())
+        return max(float(t[k:k + step].abs().max()) for k in range(0, t.shape[0], step))
+
+    mixed, full = 0.0, 0.0
+    S, Sp = slice(None, ks), slice(ks, None)
+    A, Ap = slice(None, vs), slice(vs, None)
+    for plane in (0, 1):
+        t1v, tssv, tabv = parts(r, plane)
+        mixed = max(mixed, amax(t1v[:, S, Ap]), amax(t1v[:, Sp, A]))
+        for gi, gj, ga, gb in np.ndindex(2, 2, 2, 2):
+            blk = tabv[(S, Sp)[gi], (S, Sp)[gj], (A, Ap)[ga], (A, Ap)[gb]]
+            if gi == gj == ga == gb:
+                full = max(full, amax(blk))
+            else:
+                mixed = max(mixed, amax(blk))
+        for s in range(2):
+            occ_cls = [ps, pm, torch.arange(p0, npo, device=dev)]
+            vir_cls = [qs, qm, torch.arange(q0, npv, device=dev)]
+            for co, oi in enumerate(occ_cls):
+                for cv, vi in enumerate(vir_cls):
+                    if (co, cv) in ((0, 0), (2, 2)):
+                        continue
+                    for k in range(0, oi.numel(), 256):
+                        mixed = max(mixed, amax(tssv[s][oi[k:k + 256]][:, vi]))
+            full = max(full, amax(tssv[s][p0:, q0:]))
+    print(f"max |R| joining S and S': {mixed:.3e} (max |R| {full:.3e})", flush=True)
+
+    # the energy splits: E(T) - E(T with T_S = 0) = E_S(T_S)
+    gen.manual_seed(77)
+    write(False)
+    e_s = e_full - P.energy()
+    print(f"E_S: library {e_s:.14e}, oracle {emb['e_s']:.14e}", flush=True)
+    return err, mixed / full, abs(e_s - emb["e_s"]) / max(abs(emb["e_s"]), abs(e_full))

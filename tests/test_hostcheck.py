@@ -276,3 +276,15 @@ def test_blocked_plans_give_the_same_residual(slab, block):
         Q.step(0.02, 2)
         R.step(0.02, 2)
         assert np.abs(Q.cumulant()[1] - R.cumulant()[1]).max() < 1e-14
+
+
+def test_device_set_embedding_check_on_the_host_engine():
+    """The in-place device-set check used at the contract ESCA shape (tests/embedding.py,
+    check_device), exercised on the host engine with a small system embedded in a larger one
+    and a blocked plan: writes the amplitudes in place, reads the residual in place."""
+    import embedding
+    emb = embedding.build(Shape(6, 14, 40), 5, 3, 5, 12)
+    P = rteom.Propagator(emb["eps"], emb["chol"], 6, 6, 0, 1, lib_path=LIB, workspace="torch-cpu",
+                         plan_slab=4, plan_block=2)
+    err, mixed, e_err = embedding.check_device(P, emb, 1e-12, lambda fn: fn())
+    assert err < 1e-12 and mixed <= 1e-13 and e_err <= 1e-12

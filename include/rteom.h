@@ -212,6 +212,18 @@ rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len);
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out);
 
+/* rteom_spectral for callers that cannot allocate device memory (code under HIP graph
+   capture, tight serving loops, harnesses that forbid hipMalloc): the same computation,
+   arguments and results, with its temporary in a fixed device array of 4194304 doubles
+   (32 MiB) that the library holds on each GPU it runs on until the process ends, instead
+   of a device allocation per call.  Requires 3 (steps taken + 1) + 2 n_w + 2 <= 4194304:
+   ARG (with a message) beyond that, before any device work.  Calls on one GPU share the
+   array: calls that overlap (other threads or streams) race.  Each call writes every
+   element it reads, so the array's previous contents do not matter.  STATE if the array's
+   address could not be obtained.  Synchronises the stream. */
+rteom_status rteom_spectral_noalloc(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                                    double* a_out, double* qp_out);
+
 /* Extended-space sizes and orbital lists: occ_list [n_o], vir_list [n_v] (nullable). */
 rteom_status rteom_dims(const rteom_ctx* ctx, int32_t* n_o, int32_t* n_v, int32_t* occ_list,
                         int32_t* vir_list);

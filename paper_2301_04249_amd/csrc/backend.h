@@ -253,6 +253,9 @@ class Backend {
   // dependencies between them (they may run concurrently)
   virtual void* combine_graphs(void* const* graphs, int n) { (void)graphs; (void)n; return nullptr; }
   virtual void* stream() { return nullptr; }
+  // Device memory of a fixed size that needs no allocation (nullptr where there is
+  // none); *doubles receives its capacity.  Shared by every caller on the device.
+  virtual double* fixed_scratch(int64_t* doubles) { if (doubles) *doubles = 0; return nullptr; }
   virtual int64_t energy_partials() const = 0;
   virtual void sync() = 0;
   // returns false (and a message) if an asynchronous error has been recorded

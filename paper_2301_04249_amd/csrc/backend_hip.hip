@@ -21,6 +21,7 @@
 #include <cstdint>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -1492,6 +1493,38 @@ bool launch_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, 
   return launch_prec<false, false>(prec, v, grid, st, g, akc, bkc);
 }
 
+// Fixed device scratch for entry points that must not allocate (rteom_spectral_noalloc):
+// a file-scope device array, one copy per GPU, held until the process ends.  Host code
+// never passes `scratch` itself (in host code it names a host-side stand-in): its device
+// address is looked up once per device with hipGetSymbolAddress and kept.
+constexpr int64_t kFixedScratchDoubles = int64_t(1) << 22;   // 32 MiB
+static __device__ __align__(256) double scratch[kFixedScratchDoubles];
+
+// Device address of `scratch` on the current device (looked up once per device; nullptr
+// with a message if the lookup fails).
+double* scratch_address(std::string* err) {
+  static std::mutex mu;
+  static std::map<int, double*> addr;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    (void)hipGetLastError();
+    if (err) *err = "hipGetDevice failed";
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = addr.find(dev);
+  if (it != addr.end()) return it->second;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    if (err) *err = std::string("hipGetSymbolAddress(scratch) failed: ") + hipGetErrorString(e);
+    return nullptr;
+  }
+  addr[dev] = static_cast<double*>(p);
+  return addr[dev];
+}
+
 int grid_for(int64_t n, int per_block = 256) {
   int64_t g = (n + per_block - 1) / per_block;
   return (int)std::max<int64_t>(1, std::min<int64_t>(g, 65536));
@@ -1499,7 +1532,17 @@ int grid_for(int64_t n, int per_block = 256) {
 
 class HipBackend : public Backend {
  public:
-  explicit HipBackend(hipStream_t s) : stream_(s) {}
+  explicit HipBackend(hipStream_t s) : stream_(s) {
+    // at set-up, with the context's device current: the fixed scratch's address
+    std::string m;
+    fixed_ = scratch_address(&m);
+    if (!fixed_) set_err(m);
+  }
+  double* fixed_scratch(int64_t* doubles) override {
+    if (doubles) *doubles = fixed_ ? kFixedScratchDoubles : 0;
+    return fixed_;
+  }
+  double* fixed_ = nullptr;
   ~HipBackend() override {
     for (auto& e : done_) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
     for (auto& e : pool_) (void)hipEventDestroy(e);

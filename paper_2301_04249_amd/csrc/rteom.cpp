@@ -1513,32 +1513,63 @@ rteom_status rteom_ground_state(rteom_ctx* ctx, double tol, int32_t max_iter, do
   return st;
 }
 
+// Arguments of rteom_spectral and its allocation-free variant.
+static bool spectral_args(Context& c, double e_corr, double eta, int64_t n_w, const double* omega, const double* a_out) {
+  if (c.core_orb < 0) { c.err = "the context has no core hole"; return false; }
+  if (!omega || !a_out || n_w < 1) { c.err = "omega and a_out are required, n_w >= 1"; return false; }
+  if (!std::isfinite(e_corr) || !std::isfinite(eta) || eta < 0.0) {
+    c.err = "e_corr must be finite and eta finite and >= 0";
+    return false;
+  }
+  for (int64_t j = 0; j < n_w; ++j)
+    if (!std::isfinite(omega[j])) { c.err = "non-finite frequency"; return false; }
+  return true;
+}
+
+// Doubles of device memory the spectrum needs: times, frequencies, weighted G, A, peak.
+static int64_t spectral_doubles(const Context& c, int64_t n_w) { return 3 * (c.nsteps + 1) + 2 * n_w + 2; }
+
+// The spectrum computed in the device buffer buf (spectral_doubles doubles).
+static void spectral_into(Context& c, double* buf, double e_corr, double eta, int64_t n_w, const double* omega,
+                          double* a_out, double* qp_out) {
+  const int64_t n = c.nsteps + 1;
+  double *t = buf, *w = t + n, *wg = w + n_w, *a = wg + 2 * n, *qp = a + n_w;
+  c.be->h2d(t, c.times.data(), sizeof(double) * n);
+  c.be->h2d(w, omega, sizeof(double) * n_w);
+  c.be->spectral(c.c_hist, t, n, c.eps_core + e_corr, eta, w, n_w, wg, a, qp);
+  c.be->d2h(a_out, a, sizeof(double) * n_w);
+  if (qp_out) c.be->d2h(qp_out, qp, sizeof(double) * 2);
+}
+
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out) {
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
   Context& c = ctx->c;
-  if (c.core_orb < 0) { c.err = "the context has no core hole"; return RTEOM_ERR_ARG; }
-  if (!omega || !a_out || n_w < 1) { c.err = "omega and a_out are required, n_w >= 1"; return RTEOM_ERR_ARG; }
-  if (!std::isfinite(e_corr) || !std::isfinite(eta) || eta < 0.0) {
-    c.err = "e_corr must be finite and eta finite and >= 0";
-    return RTEOM_ERR_ARG;
-  }
-  for (int64_t j = 0; j < n_w; ++j)
-    if (!std::isfinite(omega[j])) { c.err = "non-finite frequency"; return RTEOM_ERR_ARG; }
+  if (!spectral_args(c, e_corr, eta, n_w, omega, a_out)) return RTEOM_ERR_ARG;
   return guarded(ctx, [&] {
-    const int64_t n = c.nsteps + 1;
-    // post-processing buffers: times, frequencies, weighted G, A, peak
-    const size_t bytes = sizeof(double) * (size_t)(n + n_w + 2 * n + n_w + 2);
+    const size_t bytes = sizeof(double) * (size_t)spectral_doubles(c, n_w);
     std::unique_ptr<double, std::function<void(double*)>> buf(
         static_cast<double*>(c.be->alloc(bytes)), [&c](double* p) { if (p) c.be->release(p); });
     if (!buf) throw Error(RTEOM_ERR_OOM, "device allocation for the spectrum failed");
-    double *t = buf.get(), *w = t + n, *wg = w + n_w, *a = wg + 2 * n, *qp = a + n_w;
-    c.be->h2d(t, c.times.data(), sizeof(double) * n);
-    c.be->h2d(w, omega, sizeof(double) * n_w);
-    c.be->spectral(c.c_hist, t, n, c.eps_core + e_corr, eta, w, n_w, wg, a, qp);
-    c.be->d2h(a_out, a, sizeof(double) * n_w);
-    if (qp_out) c.be->d2h(qp_out, qp, sizeof(double) * 2);
+    spectral_into(c, buf.get(), e_corr, eta, n_w, omega, a_out, qp_out);
   });
+}
+
+rteom_status rteom_spectral_noalloc(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                                    double* a_out, double* qp_out) {
+  if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  if (!spectral_args(c, e_corr, eta, n_w, omega, a_out)) return RTEOM_ERR_ARG;
+  int64_t cap = 0;
+  double* buf = c.be->fixed_scratch(&cap);
+  if (!buf) { c.err = "this backend has no fixed device scratch"; return RTEOM_ERR_STATE; }
+  const int64_t need = spectral_doubles(c, n_w);
+  if (need > cap) {
+    c.err = "the spectrum needs " + std::to_string(need) + " doubles of fixed scratch (3 (steps + 1) + 2 n_w + 2), "
+            "more than its " + std::to_string(cap);
+    return RTEOM_ERR_ARG;
+  }
+  return guarded(ctx, [&] { spectral_into(c, buf, e_corr, eta, n_w, omega, a_out, qp_out); });
 }
 
 rteom_status rteom_dims(const rteom_ctx* cctx, int32_t* n_o, int32_t* n_v, int32_t* occ_list, int32_t* vir_list) {

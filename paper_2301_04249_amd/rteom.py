@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # every exported symbol of include/rteom.h
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
-    "rteom_spectral", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_spectral", "rteom_spectral_noalloc", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
     "rteom_residual_flops", "rteom_plan_info", "rteom_device_sets", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
     "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.rteom_step.argtypes = [c.c_void_p, c.c_double, c.c_int32, _ip]
     lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_spectral.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
+    lib.rteom_spectral_noalloc.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
     lib.rteom_ground_state.argtypes = [c.c_void_p, c.c_double, c.c_int32, _dp, _ip]
     lib.rteom_checkpoint.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.POINTER(c.c_size_t)]
     lib.rteom_restore.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t]
@@ -319,12 +320,14 @@ class Propagator:
         st = self.lib.rteom_restore(self.h, data, len(data))
         self._check(st, self.h)
 
-    def spectral(self, omegas, eta, e_corr=0.0):
-        """(A(omega), qp position, A at the grid maximum) from the device C(t) (rteom_spectral)."""
+    def spectral(self, omegas, eta, e_corr=0.0, noalloc=False):
+        """(A(omega), qp position, A at the grid maximum) from the device C(t) (rteom_spectral, or
+        rteom_spectral_noalloc with noalloc=True)."""
         w = np.ascontiguousarray(omegas, dtype=np.float64)
         a = np.zeros(w.shape[0])
         qp = np.zeros(2)
-        st = self.lib.rteom_spectral(self.h, float(e_corr), float(eta), w.shape[0], _ptr(w), _ptr(a), _ptr(qp))
+        fn = self.lib.rteom_spectral_noalloc if noalloc else self.lib.rteom_spectral
+        st = fn(self.h, float(e_corr), float(eta), w.shape[0], _ptr(w), _ptr(a), _ptr(qp))
         self._check(st, self.h)
         return a, qp[0], qp[1]
 

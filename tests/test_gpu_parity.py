@@ -119,7 +119,7 @@ def test_spectral_function_parity():
     assert np.abs(a2 - a).max() <= 1e-9 * np.abs(a).max()
 
 
-@pytest.mark.parametrize("prec,res_tol,c_tol,qp_tol_ev", [("fp32", 1e-5, 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-4, 1e-3)])
+@pytest.mark.parametrize("prec,res_tol,c_tol,qp_tol_ev", [("fp32", 1e-5, 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-5, 1e-3)])
 def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol, qp_tol_ev):
     """float32 and bf16x3 contractions (float64 update and C(t)): residual relative Frobenius
     error, C(t) max error over the 200-step tiny trajectory and the QP peak shift in eV, all
@@ -236,7 +236,7 @@ def test_checkpoint_restart_with_graph_replay():
     assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
 
 
-@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-5, 1e-6), ("bf16x3", 1e-4, 1e-5)])
+@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-6, 1e-6), ("bf16x3", 1e-4, 1e-5)])
 def test_ground_state_ccsd(prec, tol, solve_tol):
     """E_N^corr of the tiny workload's N-electron determinant (core_orb = -1) by
     rteom_ground_state against the oracle's Jacobi solution (relative error bound per
@@ -318,3 +318,54 @@ def test_blocked_plans_residual_parity(slab, block):
     a.step(0.02, 3)
     b.step(0.02, 3)
     assert np.abs(a.cumulant()[1] - b.cumulant()[1]).max() < 1e-13
+
+
+def _formaldehyde_golden():
+    """The oracle's 200-step trajectory of the formaldehyde-shaped core hole
+    (tests/golden/make_formaldehyde_trajectory.py): times, C(t), QP peak."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "formaldehyde_trajectory.txt")
+    qp = None
+    for line in open(path):
+        if line.startswith("# qp_peak"):
+            qp = float(line.split()[2])
+    d = np.loadtxt(path)
+    return d[:, 0], d[:, 1] + 1j * d[:, 2], qp
+
+
+@pytest.mark.parametrize("prec,c_tol,qp_tol_ev", [("fp64", 1e-8, 1e-6), ("fp32", 1e-5, 1e-4),
+                                                   ("bf16x3", 1e-5, 1e-4)])
+def test_formaldehyde_trajectory_against_oracle(prec, c_tol, qp_tol_ev):
+    """200 time steps of the formaldehyde-shaped core hole (o=8, v=110 per spin, Q=600, L
+    scaled by (16/v)^(1/2), dt = 0.025 au, 2 fixed passes per step) in each contraction
+    precision against the oracle's FP64 trajectory: C(t) max abs error within the targets
+    (FP64 1e-8, split precision 1e-5), and the QP peak of A(omega) (eta = 0.01 Eh) shifted by
+    less than the stated eV.  At this size the alpha-beta ladder and ring products are large
+    enough to take the converted-operand kernels (bf16 hi/lo planes, float planes)."""
+    t_ref, c_ref, qp_ref = _formaldehyde_golden()
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    P = _prop(eps, chol, 8, 8, 0, 1, prec=prec, fixed_iters=2, tune=False, max_steps=256)
+    P.step(0.025, 200)
+    t, c = P.cumulant()
+    assert np.allclose(t, t_ref)
+    cerr = np.abs(c - c_ref).max()
+    a, qp, _ = P.spectral(np.arange(-26.0, -14.0, 0.001), 0.01)
+    shift = (qp - qp_ref) * HARTREE_EV
+    print(f"{prec}: C(t) max abs err {cerr:.3e} (max |C| {np.abs(c_ref).max():.3f}, relative "
+          f"{cerr / np.abs(c_ref).max():.2e}); QP {qp:.9f} Eh vs oracle {qp_ref:.9f}: shift {shift:.3e} eV", flush=True)
+    assert cerr < c_tol
+    assert abs(shift) < qp_tol_ev
+
+
+def test_tolerance_driven_steps_at_the_papers_cutoff():
+    """Tolerance-driven steps with the paper's fixed-point cutoff 1e-4 (Sec. 4: the
+    micro-iterations stop at 1e-4) on the formaldehyde-shaped system: the same passes per
+    step as the oracle and C(t) within the error that cutoff allows; passes are reported."""
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    sysm = reference.n_minus_one_reference(eps, chol, 8, 8, 0, 1, lean=True)
+    P = _prop(eps, chol, 8, 8, 0, 1, tol=1e-4)
+    it = P.step(0.025, 4)
+    tr = propagate.propagate(sysm, 0.025, 4, tol=1e-4)
+    print(f"passes per step at 1e-4: library {list(it)}, oracle {list(tr.iters)}", flush=True)
+    assert np.array_equal(it, tr.iters)
+    assert np.abs(P.cumulant()[1] - tr.cumulant).max() < 1e-10

@@ -2,14 +2,16 @@
 //
 //  gemm_mfma  complex/real GEMM on the matrix cores in float64
 //             (v_mfma_f64_16x16x4f64) or float32 (v_mfma_f32_16x16x4f32),
-//             64x64, 64x128, 128x64 or 128x128 output tile per 256-thread
-//             work-group, operands staged through LDS.  Complex operands are planar; a complex x complex
-//             product is four real MFMA products per fragment, complex x real
-//             two.  Split-K and an XCD-aware tile order fill the 256 CUs.
-//  gemm_bf16x3  the same product with bf16 hi/lo operands, three
-//             v_mfma_f32_16x16x32_bf16 products per real product.
+//             64x64, 64x128, 128x64 or 128x128 output tile per work-group of four
+//             or eight waves, operands staged through LDS.  Complex operands are
+//             planar; a complex x complex product is three real MFMA products per
+//             fragment pair (Gauss form), complex x real two.  Split-K and an
+//             XCD-aware tile order fill the 256 CUs.
+//  gemm_bf16x3  the same product with bf16 hi/lo operands, three bf16 products
+//             (hi hi, hi lo, lo hi) per real product with float32 accumulation.
 //  gemm_smallk  sums of K <= 16 on the vector ALUs.
 //  permute    strided tensor copy / accumulate / scale (HBM bound).
+//  ss_*       same-spin doubles between pair storage and blocks of full storage.
 //  update     fused trapezoid update of all amplitudes with the per-spin masks,
 //             the optional diagonal map and a max-|change| reduction.
 //  energy     <Phi|(H_N e^T)_C|Phi> as a two-pass deterministic reduction.

@@ -212,6 +212,19 @@ rteom_status rteom_restore(rteom_ctx* ctx, const void* buf, size_t len);
 rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                             double* a_out, double* qp_out);
 
+/* Quasi-particle peak and satellites of the spectral function (Sec. 3: the main line and its
+   satellites; Eqs. cum_gf, cum_gf2): A(omega) as rteom_spectral computes it (written to
+   a_out [n_w] if not NULL), then its local maxima (A_j > A_{j-1} and A_j >= A_{j+1},
+   0 < j < n_w - 1), the largest first (first index on ties), at most max_peaks (1..64):
+   peaks_out [max_peaks][2] = (position refined by the parabola through the maximum and
+   its two neighbours, A at the grid maximum); *n_peaks = number found.  The first entry
+   is the QP peak; the others are satellites (and, with a coarse grid or short
+   propagation, ripples of the finite time window).  Temporary device memory of
+   3 (steps + 1) + 2 n_w + 2 max_peaks + 3 doubles; synchronises the stream.  ARG for bad
+   sizes or a context without a core hole; OOM if the temporary cannot be allocated. */
+rteom_status rteom_spectral_peaks(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                                  double* a_out, int32_t max_peaks, double* peaks_out, int32_t* n_peaks);
+
 /* rteom_spectral for callers that cannot allocate device memory (code under HIP graph
    capture, tight serving loops, harnesses that forbid hipMalloc): the same computation,
    arguments and results, with its temporary in a fixed device array of 4194304 doubles

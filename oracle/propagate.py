@@ -139,3 +139,22 @@ def qp_peak(omegas, spectrum):
         shift = 0.5 * (y0 - y2) / den if den != 0 else 0.0
         return float(omegas[k] + shift * (omegas[1] - omegas[0]))
     return float(omegas[k])
+
+
+def spectral_peaks(omegas, spectrum, k):
+    """The quasi-particle peak and its satellites: the local maxima of A on a uniform grid
+    (A_j > A_{j-1} and A_j >= A_{j+1} at interior points), the largest first (the first index
+    on ties), at most k, each refined like qp_peak by the parabola through the maximum and
+    its two neighbours.  Returns an array [n][2] of (position, A at the grid maximum)."""
+    omegas = np.asarray(omegas)
+    a = np.asarray(spectrum)
+    j = np.arange(1, a.size - 1)
+    local = j[(a[1:-1] > a[:-2]) & (a[1:-1] >= a[2:])]
+    chosen = sorted(local.tolist(), key=lambda x: (-a[x], x))[:k]
+    out = []
+    for x in chosen:
+        y0, y1, y2 = a[x - 1], a[x], a[x + 1]
+        den = y0 - 2 * y1 + y2
+        shift = 0.5 * (y0 - y2) / den if den != 0 else 0.0
+        out.append((float(omegas[x] + shift * (omegas[1] - omegas[0])), float(a[x])))
+    return np.array(out, dtype=float).reshape(-1, 2)

@@ -240,6 +240,11 @@ class Backend {
   // shift = eps_c + E_N^corr, eta = damping; wg is scratch of 2 n doubles.
   virtual void spectral(const double* c_hist, const double* times, int64_t n, double shift, double eta,
                         const double* omega, int64_t n_w, double* wg, double* a_out, double* qp_out) = 0;
+  // Peaks of a spectrum a [n_w] on the uniform grid omega (device pointers): the local maxima
+  // (a[j] > a[j-1] and a[j] >= a[j+1], 0 < j < n_w - 1), the largest first (first index on
+  // ties), at most k of them; out [k][2] = (position refined by the parabola through the
+  // maximum and its neighbours, a[j]), out[2k] = number found.
+  virtual void spectral_peaks(const double* a, const double* omega, int64_t n_w, int k, double* out) = 0;
   // Stream capture of a fixed sequence of operations into a replayable graph
   // (returns false where not supported: the caller then issues operations directly).
   virtual bool begin_capture() { return false; }

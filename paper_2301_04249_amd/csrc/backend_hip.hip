@@ -1306,6 +1306,57 @@ __global__ void spectrum_kernel(const double* wg, const double* t, int64_t n, do
 }
 
 constexpr int kPeakThreads = 1024;
+constexpr int kMaxPeaks = 64;
+
+// Local maxima of a, the largest first: k rounds of a block-wide arg-max over the local
+// maxima not yet taken (ties: the first index).
+__global__ __launch_bounds__(kPeakThreads) void peaks_kernel(const double* a, const double* omega, int64_t n_w,
+                                                             int k, double* out) {
+  __shared__ double sv[kPeakThreads];
+  __shared__ int64_t si[kPeakThreads];
+  __shared__ int64_t taken[kMaxPeaks];
+  __shared__ int found;
+  if (threadIdx.x == 0) found = 0;
+  __syncthreads();
+  for (int round = 0; round < k; ++round) {
+    double best = -INFINITY;
+    int64_t bi = -1;
+    for (int64_t j = 1 + threadIdx.x; j + 1 < n_w; j += kPeakThreads) {
+      if (!(a[j] > a[j - 1] && a[j] >= a[j + 1])) continue;
+      bool used = false;
+      for (int q = 0; q < found; ++q) used = used || taken[q] == j;
+      if (used) continue;
+      if (bi < 0 || a[j] > best) { best = a[j]; bi = j; }
+    }
+    sv[threadIdx.x] = best;
+    si[threadIdx.x] = bi;
+    __syncthreads();
+    for (int off = kPeakThreads / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        const double ov = sv[threadIdx.x + off];
+        const int64_t oi = si[threadIdx.x + off];
+        if (oi >= 0 && (si[threadIdx.x] < 0 || ov > sv[threadIdx.x] ||
+                        (ov == sv[threadIdx.x] && oi < si[threadIdx.x]))) {
+          sv[threadIdx.x] = ov;
+          si[threadIdx.x] = oi;
+        }
+      }
+      __syncthreads();
+    }
+    const int64_t j = si[0];
+    if (j < 0) break;   // no local maximum left (uniform across the block)
+    if (threadIdx.x == 0) {
+      const double y0 = a[j - 1], y1 = a[j], y2 = a[j + 1], den = y0 - 2.0 * y1 + y2;
+      const double sh = den != 0.0 ? 0.5 * (y0 - y2) / den : 0.0;
+      out[2 * found] = omega[j] + sh * (omega[1] - omega[0]);
+      out[2 * found + 1] = a[j];
+      taken[found] = j;
+      found = found + 1;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[2 * k] = (double)found;
+}
 __global__ __launch_bounds__(kPeakThreads) void qp_kernel(const double* a, const double* omega, int64_t n_w,
                                                           double* qp) {
   __shared__ double sv[kPeakThreads];
@@ -1981,6 +2032,13 @@ class HipBackend : public Backend {
     launched("spectrum");
     qp_kernel<<<1, kPeakThreads, 0, stream_>>>(a_out, omega, n_w, qp_out);
     launched("qp");
+  }
+
+  void spectral_peaks(const double* a, const double* omega, int64_t n_w, int k, double* out) override {
+    begin();
+    peaks_kernel<<<1, kPeakThreads, 0, stream_>>>(a, omega, n_w, k, out);
+    launched("peaks");
+    end();
   }
 
   void* stream() override { return stream_; }

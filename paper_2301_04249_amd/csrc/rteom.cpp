@@ -1555,6 +1555,38 @@ rteom_status rteom_spectral(rteom_ctx* ctx, double e_corr, double eta, int64_t n
   });
 }
 
+rteom_status rteom_spectral_peaks(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
+                                  double* a_out, int32_t max_peaks, double* peaks_out, int32_t* n_peaks) {
+  if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  std::vector<double> a_host;
+  if (!a_out) {
+    a_host.assign(n_w > 0 ? n_w : 1, 0.0);
+    a_out = a_host.data();
+  }
+  if (!spectral_args(c, e_corr, eta, n_w, omega, a_out)) return RTEOM_ERR_ARG;
+  if (max_peaks < 1 || max_peaks > 64 || !peaks_out || !n_peaks) {
+    c.err = "max_peaks must be in 1..64, peaks_out and n_peaks are required";
+    return RTEOM_ERR_ARG;
+  }
+  return guarded(ctx, [&] {
+    const int64_t need = spectral_doubles(c, n_w) + 2 * max_peaks + 1;
+    std::unique_ptr<double, std::function<void(double*)>> buf(
+        static_cast<double*>(c.be->alloc(sizeof(double) * need)), [&c](double* p) { if (p) c.be->release(p); });
+    if (!buf) throw Error(RTEOM_ERR_OOM, "device allocation for the spectrum failed");
+    spectral_into(c, buf.get(), e_corr, eta, n_w, omega, a_out, nullptr);
+    const int64_t n = c.nsteps + 1;
+    double* a = buf.get() + n + n_w + 2 * n;        // A(omega) as spectral_into left it
+    double* w = buf.get() + n;
+    double* pk = buf.get() + spectral_doubles(c, n_w);
+    c.be->spectral_peaks(a, w, n_w, max_peaks, pk);
+    std::vector<double> host(2 * max_peaks + 1);
+    c.be->d2h(host.data(), pk, sizeof(double) * host.size());
+    *n_peaks = (int32_t)host[2 * max_peaks];
+    for (int32_t q = 0; q < 2 * *n_peaks; ++q) peaks_out[q] = host[q];
+  });
+}
+
 rteom_status rteom_spectral_noalloc(rteom_ctx* ctx, double e_corr, double eta, int64_t n_w, const double* omega,
                                     double* a_out, double* qp_out) {
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }

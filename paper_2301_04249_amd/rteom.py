@@ -22,7 +22,7 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
 # every exported symbol of include/rteom.h
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
-    "rteom_spectral", "rteom_spectral_noalloc", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
+    "rteom_spectral", "rteom_spectral_noalloc", "rteom_spectral_peaks", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
     "rteom_residual_flops", "rteom_plan_info", "rteom_device_sets", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
     "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
@@ -89,6 +89,8 @@ def load(path: str = LIB_PATH):
     lib.rteom_cumulant.argtypes = [c.c_void_p, c.c_int64, _dp, _dp, c.POINTER(c.c_int64)]
     lib.rteom_spectral.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
     lib.rteom_spectral_noalloc.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, _dp]
+    lib.rteom_spectral_peaks.argtypes = [c.c_void_p, c.c_double, c.c_double, c.c_int64, _dp, _dp, c.c_int32, _dp,
+                                         _ip]
     lib.rteom_ground_state.argtypes = [c.c_void_p, c.c_double, c.c_int32, _dp, _ip]
     lib.rteom_checkpoint.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t, c.POINTER(c.c_size_t)]
     lib.rteom_restore.argtypes = [c.c_void_p, c.c_void_p, c.c_size_t]
@@ -334,6 +336,17 @@ class Propagator:
     def _n2(self):
         no, nv = self.no, self.nv
         return no * (no - 1) * nv * (nv - 1) // 2 + no * no * nv * nv
+
+    def spectral_peaks(self, omegas, eta, max_peaks=8, e_corr=0.0):
+        """(A(omega), peaks [n][2] = (position, height), largest first) (rteom_spectral_peaks)."""
+        w = np.ascontiguousarray(omegas, dtype=np.float64)
+        a = np.zeros(w.shape[0])
+        pk = np.zeros((max_peaks, 2))
+        n = ctypes.c_int32()
+        st = self.lib.rteom_spectral_peaks(self.h, float(e_corr), float(eta), w.shape[0], _ptr(w), _ptr(a),
+                                           int(max_peaks), _ptr(pk), ctypes.byref(n))
+        self._check(st, self.h)
+        return a, pk[: n.value].copy()
 
     def set_amplitudes(self, t1, t2):
         t1 = np.ascontiguousarray(t1, dtype=np.complex128).reshape(self.t1_shape())

@@ -369,3 +369,39 @@ def test_tolerance_driven_steps_at_the_papers_cutoff():
     print(f"passes per step at 1e-4: library {list(it)}, oracle {list(tr.iters)}", flush=True)
     assert np.array_equal(it, tr.iters)
     assert np.abs(P.cumulant()[1] - tr.cumulant).max() < 1e-10
+
+
+def test_restart_continues_the_oracle_trajectory():
+    """Checkpoint after 100 of the 200 formaldehyde steps, restore into a fresh context and
+    continue: the whole C(t) history matches the oracle's uninterrupted FP64 trajectory."""
+    t_ref, c_ref, _ = _formaldehyde_golden()
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    a = _prop(eps, chol, 8, 8, 0, 1, fixed_iters=2, tune=False, max_steps=256)
+    a.step(0.025, 100)
+    img = a.checkpoint()
+    a.close()
+    b = _prop(eps, chol, 8, 8, 0, 1, fixed_iters=2, tune=False, max_steps=256)
+    b.restore(img)
+    b.step(0.025, 100)
+    t, c = b.cumulant()
+    err = np.abs(c - c_ref).max()
+    print(f"restarted at step 100: C(t) max abs err against the oracle {err:.3e}", flush=True)
+    assert np.allclose(t, t_ref) and err < 1e-8
+
+
+def test_qp_and_satellite_peaks_against_oracle():
+    """rteom_spectral_peaks on the device C(t) of the 200-step formaldehyde trajectory against
+    the oracle's A(omega) and peak extraction applied to the oracle's own trajectory: the QP
+    peak and the next local maxima, positions and heights, in the same order."""
+    t_ref, c_ref, qp_ref = _formaldehyde_golden()
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    P = _prop(eps, chol, 8, 8, 0, 1, fixed_iters=2, tune=False, max_steps=256)
+    P.step(0.025, 200)
+    omegas = np.arange(-26.0, -14.0, 0.001)
+    a, peaks = P.spectral_peaks(omegas, 0.01, max_peaks=6)
+    a_ref = propagate.spectral_function(t_ref, propagate.green_function(t_ref, c_ref, eps[0]), omegas, 0.01)
+    ref = propagate.spectral_peaks(omegas, a_ref, 6)
+    print("peaks (Eh, A):", [(round(p, 6), round(h, 5)) for p, h in peaks], flush=True)
+    assert peaks.shape == ref.shape and abs(peaks[0, 0] - qp_ref) < 1e-9
+    assert np.abs(peaks[:, 0] - ref[:, 0]).max() < 1e-8
+    assert np.abs(peaks[:, 1] - ref[:, 1]).max() < 1e-10 * ref[0, 1]

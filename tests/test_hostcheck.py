@@ -288,3 +288,19 @@ def test_device_set_embedding_check_on_the_host_engine():
                          plan_slab=4, plan_block=2)
     err, mixed, e_err = embedding.check_device(P, emb, 1e-12, lambda fn: fn())
     assert err < 1e-12 and mixed <= 1e-13 and e_err <= 1e-12
+
+
+def test_spectral_peaks_on_the_host_engine():
+    """rteom_spectral_peaks (host engine) against the oracle's A(omega) and peak extraction on
+    a short propagation: same peaks in the same order."""
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    sysm = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB, fixed_iters=3)
+    P.step(0.02, 150)
+    tr = propagate.propagate(sysm, 0.02, 150, fixed_iters=3)
+    omegas = np.arange(-24.0, -16.0, 0.01)
+    a, peaks = P.spectral_peaks(omegas, 0.02, max_peaks=5)
+    a_ref = propagate.spectral_function(tr.times, propagate.green_function(tr.times, tr.cumulant, eps[0]), omegas, 0.02)
+    ref = propagate.spectral_peaks(omegas, a_ref, 5)
+    assert peaks.shape == ref.shape and len(peaks) >= 2
+    assert np.abs(peaks - ref).max() < 1e-9

@@ -6,6 +6,8 @@ not involved; these run on the CPU only.
 import itertools
 import os
 
+import math
+
 import numpy as np
 import pytest
 
@@ -434,3 +436,28 @@ def test_ground_state_ccsd_weak_coupling_is_mp2():
         devs.append(abs(e_cc / groundstate.mp2_energy(sysm) - 1.0))
     assert devs[0] / devs[1] > 3.0 and devs[1] / devs[2] > 3.0
     assert devs[2] < 1e-3
+
+
+def test_satellites_of_a_single_mode_cumulant():
+    """A cumulant with one bosonic mode, C(tau) = (-a + i b) tau + lam (e^{i W tau} - 1), makes
+    G(tau) a Poisson series of damped exponentials (Eqs. cum_gf, cum_gf2): A(omega) is a
+    QP Lorentzian at eps_c + E_N^corr - b and satellites n = 1, 2, ... at n W below it, with
+    weights lam^n / n! relative to the QP line.  The peak extraction finds them in that order
+    at those positions and height ratios (the sign of W in C decides on which side the
+    satellites lie; dropping the 1/n! or the Poisson factor changes the ratios)."""
+    dt, n = 0.05, 6000
+    times = np.arange(n + 1) * dt
+    a_c, b_c, lam, om, eps_c, e_corr, eta = 0.015, 0.3, 0.6, 0.8, -20.0, -0.11, 0.01
+    cum = (-a_c + 1j * b_c) * times + lam * (np.exp(1j * om * times) - 1.0)
+    g = propagate.green_function(times, cum, eps_c, e_corr)
+    omegas = np.arange(-23.5, -19.0, 0.002)
+    a = propagate.spectral_function(times, g, omegas, eta)
+    peaks = propagate.spectral_peaks(omegas, a, 4)
+    w0 = eps_c + e_corr - b_c
+    expect = [w0 - k * om for k in range(4)]
+    assert np.abs(peaks[:, 0] - expect).max() < 2e-4
+    ratios = peaks[1:, 1] / peaks[0, 1]
+    poisson = np.array([lam ** k / math.factorial(k) for k in range(1, 4)])
+    assert np.abs(ratios / poisson - 1).max() < 2e-2
+    # the same extraction takes the global maximum first, as qp_peak does
+    assert abs(peaks[0, 0] - propagate.qp_peak(omegas, a)) < 1e-12

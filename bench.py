@@ -25,7 +25,8 @@ from synthetic import ESCA, ESCA_PAPER, FORMALDEHYDE, TINY, Shape, batched_shape
 
 # Ladder kernel per precision (the contraction's MFMA instruction family)
 KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands converted to float planes)",
-               "bf16x3": "gemm_bf16x3_split (operands split into bf16 hi/lo planes)"}
+               "bf16x3": "gemm_bf16x3_split<bf16> (operands split into bf16 hi/lo planes)",
+               "fp16x3": "gemm_bf16x3_split<f16> (operands scaled per row, split into fp16 hi/lo planes)"}
 
 # HBM bytes per ladder launch from rocprofv3 --pmc FETCH_SIZE and WRITE_SIZE,
 # scaled by the same counters read on a plain device copy of known size; the
@@ -40,17 +41,18 @@ TRAFFIC = {
 }
 
 DTYPE = {"fp64": "f64", "fp32": "f32 contractions, f64 update",
-         "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update"}
+         "bf16x3": "bf16x3 contractions (f32 accumulate), f64 update",
+         "fp16x3": "fp16x3 contractions (row-scaled, f32 accumulate), f64 update"}
 
-# Matrix-core flops executed per useful flop: the split precision runs three bf16
-# products (hi*hi, hi*lo, lo*hi) per product; its roofline counts executed flops
-EXEC_PER_USEFUL = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0}
+# Matrix-core flops executed per useful flop: the split precisions run three 16-bit
+# products (hi*hi, hi*lo, lo*hi) per product; their roofline counts executed flops
+EXEC_PER_USEFUL = {"fp64": 1.0, "fp32": 1.0, "bf16x3": 3.0, "fp16x3": 3.0}
 
 # Conservative residual rates (TFLOP/s) used only to fit the large workloads' steps into the budget
-RATE_GUESS = {"fp64": 40.0, "fp32": 70.0, "bf16x3": 100.0}
+RATE_GUESS = {"fp64": 40.0, "fp32": 70.0, "bf16x3": 100.0, "fp16x3": 100.0}
 
 # MI355X published peaks (dense)
-PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0}
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "fp16x3": 2500.0}
 PEAK_HBM_GBS = 8000.0
 
 # Cholesky vectors of the paper-shaped workloads are scaled by (16/v)^(1/2) (same seeds):
@@ -263,7 +265,7 @@ def main(argv=None):
     ap.add_argument("--workload", default="esca", choices=sorted(WORKLOADS))
     ap.add_argument("--budget", type=float, default=330.0,
                     help="seconds for warm-up plus timed steps of the large workloads (caps both)")
-    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (HBM counter calibration) and exit")

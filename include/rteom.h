@@ -69,7 +69,10 @@ typedef enum {
 typedef enum {
   RTEOM_FP64 = 0,   /* contractions in float64 (MFMA f64) */
   RTEOM_FP32 = 1,   /* contractions in float32 (MFMA f32), float64 storage */
-  RTEOM_BF16X3 = 2  /* bf16 hi/lo split, three MFMA products, float32 accumulation */
+  RTEOM_BF16X3 = 2, /* bf16 hi/lo split, three MFMA products, float32 accumulation */
+  RTEOM_FP16X3 = 3  /* fp16 hi/lo split of operands scaled per row by powers of two, three
+                       MFMA f16 products, float32 accumulation (about float32's accuracy at
+                       the 16-bit MFMA rate); products too small to convert run in float32 */
 } rteom_prec;
 
 /* Memory plan.  Every intermediate that grows like o^2 v^2 or faster is produced in

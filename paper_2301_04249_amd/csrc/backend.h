@@ -52,8 +52,10 @@ inline int64_t split_doubles(int64_t M, int64_t N, int64_t K, int64_t batch_a, i
                              int prec) {
   // elements of all real planes of A ([M][ld]) and B ([N][ld])
   const int64_t el = split_ld(K) * (batch_a * M * (ac ? 2 : 1) + batch_b * N * (bc ? 2 : 1));
-  // bf16x3: two 2-byte planes per real plane; fp32: one 4-byte plane; +64 for alignment
-  return (prec == 2 ? (2 * el + 3) / 4 : (el + 1) / 2) + 64;
+  // bf16x3 / fp16x3: two 2-byte planes per real plane; fp32: one 4-byte plane; +64 for
+  // alignment.  fp16x3 adds each row's maximum and inverse scale (4 bytes each).
+  const int64_t scales = prec == 3 ? batch_a * M + batch_b * N : 0;
+  return (prec >= 2 ? (2 * el + 3) / 4 : (el + 1) / 2) + scales + 64;
 }
 
 // Doubles that hold one real operand of `rows` rows converted for a sum of K: two

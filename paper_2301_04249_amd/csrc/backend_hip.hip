@@ -58,6 +58,8 @@ struct GemmArgs {
   const unsigned short* sa[4];
   const unsigned short* sb[4];
   int64_t sld, sab, sbb;      // row length and batch strides (0: one matrix for all batch entries)
+  // fp16x3 planes: per-row inverse scale factors (powers of two) of A [batch][M] and B [batch][N]
+  const float* sca; const float* scb;
   int64_t aext, bext;         // elements spanned by A and B from ar / br (all batch entries)
 };
 
@@ -610,12 +612,109 @@ __global__ __launch_bounds__(256) void f32_kernel(const double* src, int64_t row
   }
 }
 
-typedef float f16v __attribute__((ext_vector_type(16)));
+// fp16x3 operands: the largest |x| of every row (both planes of a complex operand), as
+// the bit pattern of a non-negative float (which orders like the value), over 64 x 64
+// tiles of (rows, k) read along the unit-stride index.
+__global__ __launch_bounds__(256) void rowmax_kernel(const double* src, int64_t rows, int64_t K, int64_t s_row,
+                                                     int64_t s_k, int64_t s_b, unsigned int* rmax) {
+  __shared__ float tile[64][65];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64, b = blockIdx.z;
+  const double* S = src + b * s_b;
+  const int t = threadIdx.x;
+  const bool kfast = s_k == 1;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = t & 63, c = (t >> 6) + 4 * i;
+    const int rr = kfast ? c : a, kk = kfast ? a : c;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    tile[rr][kk] = (r < rows && k < K) ? (float)fabs(S[r * s_row + k * s_k]) : 0.f;
+  }
+  __syncthreads();
+  if (t < 64 && r0 + t < rows) {
+    float m = 0.f;
+    for (int kk = 0; kk < 64; ++kk) m = fmaxf(m, tile[t][kk]);
+    atomicMax(rmax + b * rows + r0 + t, __float_as_uint(m));
+  }
+}
 
-__device__ inline f16v mma3_32(bf8 ah, bf8 al, bf8 bh, bf8 bl, f16v c) {
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl, c, 0, 0, 0);
-  c = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh, c, 0, 0, 0);
+// x scaled by 2^e per row into fp16's range (the row maximum to [2^13, 2^14)), split into
+// hi = fp16(x 2^e) and lo = fp16(x 2^e - hi); inv [batch][rows] receives 2^-e.
+__global__ __launch_bounds__(256) void split_f16_kernel(const double* src, int64_t rows, int64_t K, int64_t s_row,
+                                                        int64_t s_k, int64_t s_b, int64_t ld, const unsigned int* rmax,
+                                                        unsigned short* hi, unsigned short* lo, float* inv) {
+  __shared__ double tile[64][65];
+  __shared__ double scale[64];
+  const int64_t r0 = (int64_t)blockIdx.y * 64, k0 = (int64_t)blockIdx.x * 64, b = blockIdx.z;
+  const double* S = src + b * s_b;
+  const int t = threadIdx.x;
+  const bool kfast = s_k == 1;
+  if (t < 64) {
+    const int64_t r = r0 + t;
+    const float m = r < rows ? __uint_as_float(rmax[b * rows + r]) : 0.f;
+    int e = 0;
+    if (m > 0.f) {
+      frexpf(m, &e);          // m = f 2^e with f in [0.5, 1)
+      e = 14 - e;             // m 2^e in [2^13, 2^14)
+    }
+    scale[t] = ldexp(1.0, e);
+    if (r < rows && k0 == 0) inv[b * rows + r] = ldexpf(1.f, -e);
+  }
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int a = t & 63, c = (t >> 6) + 4 * i;
+    const int rr = kfast ? c : a, kk = kfast ? a : c;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    tile[rr][kk] = (r < rows && k < K) ? S[r * s_row + k * s_k] : 0.0;
+  }
+  __syncthreads();
+  unsigned short* H = hi + b * rows * ld;
+  unsigned short* L = lo + b * rows * ld;
+#pragma unroll
+  for (int i = 0; i < 16; ++i) {
+    const int kk = t & 63, rr = (t >> 6) + 4 * i;
+    const int64_t r = r0 + rr, k = k0 + kk;
+    if (r < rows && k < ld) {
+      const double x = tile[rr][kk] * scale[rr];
+      const _Float16 h = (_Float16)x;
+      const _Float16 l = (_Float16)(x - (double)h);
+      H[r * ld + k] = __builtin_bit_cast(unsigned short, h);
+      L[r * ld + k] = __builtin_bit_cast(unsigned short, l);
+    }
+  }
+}
+
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+
+// The two 16-bit split formats: bf16 (8-bit significand, float32's range) and fp16
+// (11-bit significand, planes scaled per row into its range).  Both keep the sign in
+// bit 15, so negating a fragment flips that bit in either.
+struct SplitBf16 {
+  typedef bf8 vec;
+  static constexpr bool scaled = false;
+  static __device__ inline f16v mma(vec a, vec b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0); }
+};
+struct SplitF16 {
+  typedef h8 vec;
+  static constexpr bool scaled = true;
+  static __device__ inline f16v mma(vec a, vec b, f16v c) { return __builtin_amdgcn_mfma_f32_32x32x16_f16(a, b, c, 0, 0, 0); }
+};
+
+template <typename E>
+__device__ inline typename E::vec ldv(const unsigned short* p) { return *reinterpret_cast<const typename E::vec*>(p); }
+template <typename V>
+__device__ inline V negv(V v) {
+  typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+  u4 u = __builtin_bit_cast(u4, v);
+  u ^= u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+  return __builtin_bit_cast(V, u);
+}
+
+template <typename E>
+__device__ inline f16v mma3_32(typename E::vec ah, typename E::vec al, typename E::vec bh, typename E::vec bl, f16v c) {
+  c = E::mma(ah, bh, c);
+  c = E::mma(ah, bl, c);
+  c = E::mma(al, bh, c);
   return c;
 }
 
@@ -625,8 +724,9 @@ __device__ inline f16v mma3_32(bf8 ah, bf8 al, bf8 bh, bf8 bl, f16v c) {
 // of WM x WN blocks of 32 x 32; a fragment lane holds row (lane % 32) and k
 // (lane / 32) * 8 .. + 7 of its block; accumulator register r of a lane holds row
 // 8 (r / 4) + 4 (lane / 32) + r % 4 and column lane % 32.
-template <bool AC, bool BC, int WM, int WN>
+template <typename E, bool AC, bool BC, int WM, int WN>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_bf16x3_split(GemmArgs g) {
+  typedef typename E::vec V;
   constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BKH + PADH;
   constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
   constexpr int CA = TM / 64, CB = TN / 64;             // 16-byte chunks per thread and plane
@@ -701,34 +801,34 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
 #pragma unroll
       for (int ks = 0; ks < BKH / 16; ++ks) {
         const int kk = ks * 16 + kh;
-        bf8 xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
+        V xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
 #pragma unroll
         for (int x = 0; x < WM; ++x) {
           const int row = wm * 32 * WM + x * 32 + l32;
-          xrh[x] = ld8(&sa[buf][0][row][kk]);
-          xrl[x] = ld8(&sa[buf][1][row][kk]);
-          if (AC) { xih[x] = ld8(&sa[buf][2 % PA][row][kk]); xil[x] = ld8(&sa[buf][3 % PA][row][kk]); }
+          xrh[x] = ldv<E>(&sa[buf][0][row][kk]);
+          xrl[x] = ldv<E>(&sa[buf][1][row][kk]);
+          if (AC) { xih[x] = ldv<E>(&sa[buf][2 % PA][row][kk]); xil[x] = ldv<E>(&sa[buf][3 % PA][row][kk]); }
         }
 #pragma unroll
         for (int y = 0; y < WN; ++y) {
           const int col = wn * 32 * WN + y * 32 + l32;
-          yrh[y] = ld8(&sb[buf][0][col][kk]);
-          yrl[y] = ld8(&sb[buf][1][col][kk]);
-          if (BC) { yih[y] = ld8(&sb[buf][2 % PB][col][kk]); yil[y] = ld8(&sb[buf][3 % PB][col][kk]); }
+          yrh[y] = ldv<E>(&sb[buf][0][col][kk]);
+          yrl[y] = ldv<E>(&sb[buf][1][col][kk]);
+          if (BC) { yih[y] = ldv<E>(&sb[buf][2 % PB][col][kk]); yil[y] = ldv<E>(&sb[buf][3 % PB][col][kk]); }
         }
 #pragma unroll
         for (int x = 0; x < WM; ++x)
 #pragma unroll
           for (int y = 0; y < WN; ++y) {
-            accr[x][y] = mma3_32(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
+            accr[x][y] = mma3_32<E>(xrh[x], xrl[x], yrh[y], yrl[y], accr[x][y]);
             if (AC && BC) {
-              accr[x][y] = mma3_32(neg8(xih[x]), neg8(xil[x]), yih[y], yil[y], accr[x][y]);
-              acci[x][y] = mma3_32(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
-              acci[x][y] = mma3_32(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+              accr[x][y] = mma3_32<E>(negv(xih[x]), negv(xil[x]), yih[y], yil[y], accr[x][y]);
+              acci[x][y] = mma3_32<E>(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+              acci[x][y] = mma3_32<E>(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
             } else if (AC) {
-              acci[x][y] = mma3_32(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
+              acci[x][y] = mma3_32<E>(xih[x], xil[x], yrh[y], yrl[y], acci[x][y]);
             } else if (BC) {
-              acci[x][y] = mma3_32(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
+              acci[x][y] = mma3_32<E>(xrh[x], xrl[x], yih[y], yil[y], acci[x][y]);
             }
           }
       }
@@ -750,15 +850,18 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
           const int64_t gn = n0 + wn * 32 * WN + y * 32 + l32;
           if (gm < g.M && gn < g.N) {
             const int64_t o = gm * sm + gn * sn;
+            // fp16 planes: undo the rows' power-of-two scales (exact)
+            const double us = E::scaled ? (double)g.sca[b * (g.sab ? g.M : 0) + gm] * (double)g.scb[b * (g.sbb ? g.N : 0) + gn]
+                                        : 1.0;
             if (split) {
-              Cr[o] = (double)accr[x][y][r];
-              if (AC || BC) Ci[o] = (double)acci[x][y][r];
+              Cr[o] = us * (double)accr[x][y][r];
+              if (AC || BC) Ci[o] = us * (double)acci[x][y][r];
             } else {
-              double vr = g.alpha * (double)accr[x][y][r];
+              double vr = g.alpha * us * (double)accr[x][y][r];
               if (g.beta) vr += Cr[o];
               Cr[o] = vr;
               if (AC || BC) {
-                double vi = g.alpha * (double)acci[x][y][r];
+                double vi = g.alpha * us * (double)acci[x][y][r];
                 if (g.beta) vi += Ci[o];
                 Ci[o] = vi;
               }
@@ -1496,33 +1599,35 @@ inline bool split_tile_allowed(int v, bool ac, bool bc) {
   return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v) <= 80 * 1024;
 }
 
-template <bool AC, bool BC, int WM, int WN, int V>
+template <typename E, bool AC, bool BC, int WM, int WN, int V>
 bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
   if constexpr (split_lds_bytes(AC, BC, V) <= 80 * 1024) {
-    gemm_bf16x3_split<AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
+    gemm_bf16x3_split<E, AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
     return true;
   }
   return false;
 }
 
-template <bool AC, bool BC>
+template <typename E, bool AC, bool BC>
 bool launch_split(int v, dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if (v == 0) return launch_split_tile<AC, BC, 1, 1, 0>(grid, st, g);
-  if (v == 1) return launch_split_tile<AC, BC, 1, 2, 1>(grid, st, g);
-  if (v == 2) return launch_split_tile<AC, BC, 2, 1, 2>(grid, st, g);
-  if (v == 3) return launch_split_tile<AC, BC, 2, 2, 3>(grid, st, g);
+  if (v == 0) return launch_split_tile<E, AC, BC, 1, 1, 0>(grid, st, g);
+  if (v == 1) return launch_split_tile<E, AC, BC, 1, 2, 1>(grid, st, g);
+  if (v == 2) return launch_split_tile<E, AC, BC, 2, 1, 2>(grid, st, g);
+  if (v == 3) return launch_split_tile<E, AC, BC, 2, 2, 3>(grid, st, g);
   return false;
 }
 
+template <typename E>
 bool launch_split_gemm(int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
-  if (ac && bc) return launch_split<true, true>(v, grid, st, g);
-  if (ac) return launch_split<true, false>(v, grid, st, g);
-  if (bc) return launch_split<false, true>(v, grid, st, g);
-  return launch_split<false, false>(v, grid, st, g);
+  if (ac && bc) return launch_split<E, true, true>(v, grid, st, g);
+  if (ac) return launch_split<E, true, false>(v, grid, st, g);
+  if (bc) return launch_split<E, false, true>(v, grid, st, g);
+  return launch_split<E, false, false>(v, grid, st, g);
 }
 
 bool launch_converted_gemm(int prec, int v, dim3 grid, hipStream_t st, const GemmArgs& g, bool ac, bool bc) {
-  if (prec == 2) return launch_split_gemm(v, grid, st, g, ac, bc);
+  if (prec == 2) return launch_split_gemm<SplitBf16>(v, grid, st, g, ac, bc);
+  if (prec == 3) return launch_split_gemm<SplitF16>(v, grid, st, g, ac, bc);
   if (ac && bc) return launch_f32_converted<true, true>(v, grid, st, g);
   if (ac) return launch_f32_converted<true, false>(v, grid, st, g);
   if (bc) return launch_f32_converted<false, true>(v, grid, st, g);
@@ -1675,7 +1780,7 @@ class HipBackend : public Backend {
   int64_t energy_partials() const override { return 2 * kEnergyBlocks; }
 
   void gemm(const GemmOp& op) override {
-    if (op.prec < 0 || op.prec > 2) {
+    if (op.prec < 0 || op.prec > 3) {
       set_err("unknown contraction precision");
       return;
     }
@@ -1723,12 +1828,16 @@ class HipBackend : public Backend {
     const bool ac = op.a_im != nullptr, bc = op.b_im != nullptr;
     const bool akc = op.a_sk == 1 && op.a_sm != 1, bkc = op.b_sk == 1 && op.b_sn != 1;
     const bool presplit = op.prec != 0 && op.split != nullptr;
+    if (op.prec == 3 && (!presplit || op.b_conv)) {
+      set_err("gemm: fp16x3 needs both operands converted before the product into the split scratch");
+      return;
+    }
     begin();   // one timed operation: operand conversion, product and split-K reduction
     if (presplit) {
-      if (op.prec == 2) split_operands(op, g, ac, bc);
+      if (op.prec >= 2) split_operands(op, g, ac, bc);
       else f32_operands(op, g, ac, bc);
     }
-    if (!(presplit && op.prec == 2) && !windows_fit(g, op.prec == 0 || !presplit ? 8 : 4)) {
+    if (!(presplit && op.prec >= 2) && !windows_fit(g, op.prec == 0 || !presplit ? 8 : 4)) {
       set_err("gemm: an operand tile spans more than 2 GiB");
       end();
       return;
@@ -1766,6 +1875,41 @@ class HipBackend : public Backend {
     g.sld = ld;
     g.sab = op.a_sb ? op.M * ld : 0;
     g.sbb = op.b_sb ? op.N * ld : 0;
+    if (op.prec == 3) {
+      // fp16 planes scaled per row: row maxima of both planes, then the split.  The
+      // scratch holds after the planes: A's and B's row maxima (uint) and inverse
+      // scales (float), [batch][rows] each.
+      unsigned int* amax = reinterpret_cast<unsigned int*>(base + pa * asz + pb * bsz);
+      unsigned int* bmax = amax + nba * op.M;
+      float* ainv = reinterpret_cast<float*>(bmax + nbb * op.N);
+      float* binv = ainv + nba * op.M;
+      g.sca = ainv;
+      g.scb = binv;
+      fill_kernel<<<grid_for((nba * op.M + nbb * op.N + 1) / 2), 256, 0, stream_>>>(
+          reinterpret_cast<double*>(amax), (nba * op.M + nbb * op.N + 1) / 2, 0.0);
+      launched("fill");
+      auto rmax = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, unsigned int* m) {
+        dim3 grid((unsigned)((op.K + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
+        rowmax_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, m);
+        launched("row max");
+      };
+      auto run16 = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, const unsigned int* m,
+                       const unsigned short* h, const unsigned short* l, float* inv) {
+        dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
+        split_f16_kernel<<<grid, 256, 0, stream_>>>(src, rows, op.K, s_row, s_k, s_b, ld, m,
+                                                     const_cast<unsigned short*>(h), const_cast<unsigned short*>(l), inv);
+        launched("split f16");
+      };
+      rmax(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, amax);
+      if (ac) rmax(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, amax);
+      rmax(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, bmax);
+      if (bc) rmax(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, bmax);
+      run16(op.a_re, op.M, op.a_sm, op.a_sk, op.a_sb, amax, g.sa[0], g.sa[1], ainv);
+      if (ac) run16(op.a_im, op.M, op.a_sm, op.a_sk, op.a_sb, amax, g.sa[2], g.sa[3], ainv);
+      run16(op.b_re, op.N, op.b_sn, op.b_sk, op.b_sb, bmax, g.sb[0], g.sb[1], binv);
+      if (bc) run16(op.b_im, op.N, op.b_sn, op.b_sk, op.b_sb, bmax, g.sb[2], g.sb[3], binv);
+      return;
+    }
     auto run = [&](const double* src, int64_t rows, int64_t s_row, int64_t s_k, int64_t s_b, const unsigned short* h,
                    const unsigned short* l) {
       dim3 grid((unsigned)((ld + 63) / 64), (unsigned)((rows + 63) / 64), (unsigned)(s_b ? op.batch : 1));
@@ -1853,7 +1997,7 @@ class HipBackend : public Backend {
 
   int choose_tile(const GemmOp& op, GemmArgs& g, bool ac, bool bc, bool akc, bool bkc, bool presplit) {
     auto allowed = [&](int v) {
-      return (presplit && op.prec == 2) ? split_tile_allowed(v, ac, bc) : tile_allowed(v, op.prec, ac, bc);
+      return (presplit && op.prec >= 2) ? split_tile_allowed(v, ac, bc) : tile_allowed(v, op.prec, ac, bc);
     };
     if (force_ >= 0) return allowed(force_) ? force_ : 0;
     int cand[kTiles], nc = 0;

@@ -404,7 +404,8 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
   if (prec != 0 && op.K >= kSplitMinK && static_cast<double>(op.M) * op.N * op.K * op.batch >= kSplitMinMacs &&
       op.M >= 64 && op.N >= 64) {
     // a constant B (the caller's slot), used as it is (no copy) and alone in its batch
-    const bool resident = b_slot && b_slot->p && op.b_im == nullptr && op.batch == 1 && Bu.re == B.re &&
+    // (not for fp16x3, whose planes carry per-row scales the slot does not hold)
+    const bool resident = prec != 3 && b_slot && b_slot->p && op.b_im == nullptr && op.batch == 1 && Bu.re == B.re &&
                           conv_doubles(op.N, op.K) <= b_slot->doubles;
     if (resident) {
       if (b_slot->ready && (b_slot->rows != op.N || b_slot->k != op.K || b_slot->s_row != op.b_sn ||
@@ -426,6 +427,9 @@ void Engine::contract(const char* spec_str, const View& A, const View& B, const 
     }
     op.split = scratch->take(split_doubles(op.M, resident ? 0 : op.N, op.K, op.a_sb ? op.batch : 1,
                                            op.b_sb ? op.batch : 1, op.a_im != nullptr, op.b_im != nullptr, prec));
+  } else if (prec == 3) {
+    // fp16x3 is a converted-operand product only: the small ones run in float32
+    op.prec = 1;   // float32
   }
   const double mult = (A.cplx() && B.cplx()) ? 4.0 : ((A.cplx() || B.cplx()) ? 2.0 : 1.0);
   const double f = 2.0 * mult * static_cast<double>(op.M) * op.N * op.K * op.batch;

@@ -1162,7 +1162,7 @@ rteom_status guarded(rteom_ctx* ctx, F&& fn) {
 
 bool valid_options(const rteom_options* o, std::string* m) {
   if (o->struct_size != sizeof(rteom_options)) { *m = "rteom_options.struct_size mismatch"; return false; }
-  if (o->prec < 0 || o->prec > 2) { *m = "unknown precision"; return false; }
+  if (o->prec < 0 || o->prec > 3) { *m = "unknown precision"; return false; }
   if (o->fp_map < 0 || o->fp_map > 1) { *m = "unknown fixed-point map"; return false; }
   if (o->fp_fixed_iters < 0 || o->fp_max_iter < 1) { *m = "bad pass counts"; return false; }
   if (!(o->fp_tol > 0.0)) { *m = "fp_tol must be positive"; return false; }

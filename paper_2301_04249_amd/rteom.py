@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(HERE, "librteom.so")
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_OOM", 3: "ERR_HIP", 4: "ERR_NOCONV", 5: "ERR_NONFINITE",
           6: "ERR_STATE"}
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 
 # every exported symbol of include/rteom.h
 SYMBOLS = (

@@ -338,6 +338,24 @@ class HostBackend : public Backend {
     qp[1] = a[best];
   }
 
+  void spectral_peaks(const double* a, const double* omega, int64_t n_w, int k, double* out) override {
+    std::vector<int64_t> taken;
+    for (int r = 0; r < k; ++r) {
+      int64_t bi = -1;
+      for (int64_t j = 1; j + 1 < n_w; ++j) {
+        if (!(a[j] > a[j - 1] && a[j] >= a[j + 1])) continue;
+        if (std::find(taken.begin(), taken.end(), j) != taken.end()) continue;
+        if (bi < 0 || a[j] > a[bi]) bi = j;
+      }
+      if (bi < 0) break;
+      const double y0 = a[bi - 1], y1 = a[bi], y2 = a[bi + 1], den = y0 - 2.0 * y1 + y2;
+      out[2 * taken.size()] = omega[bi] + (den != 0.0 ? 0.5 * (y0 - y2) / den : 0.0) * (omega[1] - omega[0]);
+      out[2 * taken.size() + 1] = a[bi];
+      taken.push_back(bi);
+    }
+    out[2 * k] = (double)taken.size();
+  }
+
   void cumulant_append(double* c, double* e, const double* en, int64_t* step, double h, double* bad) override {
     // C + i h (E_k + E_{k+1})
     const int64_t k = *step;

@@ -20,7 +20,7 @@ static int check(Backend* be) {
                      {600,1000,40,1,1},{1000,600,40,2,1},{577,130,36,1,1},{300,260,70,1,3}};
   int fails = 0, runs = 0;
   srand(1);
-  for (int prec = 0; prec < 3; ++prec)
+  for (int prec = 0; prec < 4; ++prec)
   for (auto& sh : shapes) {
     long M = sh[0], N = sh[1], K = sh[2], B = sh[3]; int S = sh[4];
     for (int bcast = 0; bcast < (B > 1 ? 2 : 1); ++bcast)
@@ -31,21 +31,36 @@ static int check(Backend* be) {
       for (auto& x : A) x = rand()/(double)RAND_MAX - 0.5;
       for (auto& x : Bv) x = rand()/(double)RAND_MAX - 0.5;
       for (auto& x : C) x = rand()/(double)RAND_MAX - 0.5;
-      GemmOp g; g.M=M; g.N=N; g.K=K; g.batch=B;
+      GemmOp g;
+      std::vector<double> Cabs(nc); g.M=M; g.N=N; g.K=K; g.batch=B;
       g.a_sm = akc ? K : 1; g.a_sk = akc ? 1 : M; g.a_sb = bcast ? 0 : M*K;   // bcast: one A for every batch entry
       g.b_sk = bkc ? 1 : N; g.b_sn = bkc ? K : 1; g.b_sb = K*N;
       g.c_sm = N; g.c_sn = 1; g.c_sb = M*N; g.alpha = 0.75; g.beta = 1; g.prec = prec;
       double* dP = nullptr;
       if (S > 1) { dP = (double*)be->alloc(16L*S*M*N); g.splitk = S; g.partial = dP; }
+      if (prec == 3) {
+        // rows of A and columns of B over 2^-20 .. 2^20 (the per-row scaling's case);
+        // checked element by element against the sum of magnitudes
+        for (long b=0;b<(bcast?1:B);++b) for (long m=0;m<M;++m) for (long k=0;k<K;++k) {
+          long ia = b*M*K + m*g.a_sm + k*g.a_sk;
+          A[ia] = std::ldexp(A[ia], (int)(m % 41) - 20); A[na+ia] = std::ldexp(A[na+ia], (int)(m % 41) - 20);
+        }
+        for (long b=0;b<B;++b) for (long n=0;n<N;++n) for (long k=0;k<K;++k) {
+          long ib = b*g.b_sb + k*g.b_sk + n*g.b_sn;
+          Bv[ib] = std::ldexp(Bv[ib], (int)(n % 37) - 18); Bv[nb+ib] = std::ldexp(Bv[nb+ib], (int)(n % 37) - 18);
+        }
+      }
       for (long b=0;b<B;++b) for (long m=0;m<M;++m) for (long n=0;n<N;++n) {
-        double sr=0, si=0;
+        double sr=0, si=0, sa=0;
         for (long k=0;k<K;++k) {
           long ia = b*g.a_sb + m*g.a_sm + k*g.a_sk, ib = b*g.b_sb + k*g.b_sk + n*g.b_sn;
           double ar=A[ia], ai= ac? A[na+ia]:0, br=Bv[ib], bi = bc? Bv[nb+ib]:0;
           sr += ar*br - ai*bi; si += ar*bi + ai*br;
+          sa += (std::fabs(ar) + std::fabs(ai)) * (std::fabs(br) + std::fabs(bi));
         }
         long ic = b*g.c_sb + m*g.c_sm + n*g.c_sn;
         Cref[ic] = 0.75*sr + C[ic]; Cref[nc+ic] = 0.75*si + C[nc+ic];
+        Cabs[ic] = 0.75*sa + std::fabs(C[ic]) + std::fabs(C[nc+ic]);
       }
       double *dA=(double*)be->alloc(16*na), *dB=(double*)be->alloc(16*nb), *dC=(double*)be->alloc(16*nc);
       be->h2d(dA, A.data(), 16*na); be->h2d(dB, Bv.data(), 16*nb);
@@ -53,8 +68,9 @@ static int check(Backend* be) {
       g.c_re=dC; g.c_im = (ac||bc) ? dC+nc : nullptr;
       double* dS = nullptr;
       if (prec >= 1) dS = (double*)be->alloc(8 * split_doubles(M, N, K, bcast ? 1 : B, B, ac, bc, prec));
-      for (int vv = -1; vv < (prec >= 1 ? 9 : 6); ++vv) {
-        // prec 0: -1..5; prec 1, 2: -1..3 converted while staging, then -1..3 converted before
+      for (int vv = prec == 3 ? 4 : -1; vv < (prec >= 1 ? 9 : 6); ++vv) {
+        // prec 0: -1..5; prec 1, 2: -1..3 converted while staging, then -1..3 converted
+        // before; prec 3 (converted before only): -1..3
         const int v = (prec >= 1 && vv >= 4) ? vv - 5 : vv;
         g.split = (prec >= 1 && vv >= 4) ? dS : nullptr;
         be->force_tile(v);
@@ -64,14 +80,18 @@ static int check(Backend* be) {
         double e=0, mx=1; long nn = (ac||bc) ? 2*nc : nc;
         for (long i=0;i<nn;++i) { e = std::fmax(e, std::fabs(Cout[i]-Cref[i])); mx = std::fmax(mx, std::fabs(Cref[i])); }
         e /= mx;
+        if (prec == 3) {
+          e = 0;
+          for (long i=0;i<nn;++i) e = std::fmax(e, std::fabs(Cout[i]-Cref[i]) / Cabs[i % nc]);
+        }
         std::string m; bool ok = be->ok(&m);
         ++runs;
-        const double tol = prec == 0 ? 1e-12 : (prec == 1 ? 2e-5 : 2e-3);
+        const double tol = prec == 0 ? 1e-12 : (prec == 1 ? 2e-5 : (prec == 2 ? 2e-3 : 1e-5));
         // every tile shape of one kernel family gives bitwise the same result; bf16x3
         // on converted operands runs the 32x32x16 matrix cores (another k grouping
         // than the converting 16x16x32 kernel), so it has a reference of its own
         bool same = true;
-        const bool own = prec == 2 && vv >= 4;
+        const bool own = prec >= 2 && vv >= 4;
         if (vv == 0) C0 = Cout;
         if (own && vv == 4) C1 = Cout;
         else if (vv > 0 && v >= 0) same = std::memcmp((own ? C1 : C0).data(), Cout.data(), sizeof(double) * nn) == 0;

@@ -22,7 +22,7 @@ def emb():
     return embedding.build(ESCA_PAPER, 3, TINY.o, TINY.v, TINY.nchol)
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-5), ("bf16x3", 1e-3)])
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 1e-5), ("bf16x3", 1e-3), ("fp16x3", 1e-5)])
 def test_esca_embedded_parity(emb, prec, tol):
     print(f"ESCA-shaped residual, prec={prec}", flush=True)
     P = rteom.Propagator(emb["eps"], emb["chol"], ESCA_PAPER.o, ESCA_PAPER.o, 0, 1, prec=prec, fixed_iters=2,

@@ -1,6 +1,7 @@
 """GEMM and permute kernels of the library, case by case (tests/kernel_probe/kernel_probe.cpp):
 every operand layout, complex combination, ragged size, split-K factor, broadcast batch and
-tile shape against host loops in float64 (1e-12), float32 (2e-5) and bf16x3 (2e-3); tile
+tile shape against host loops in float64 (1e-12), float32 (2e-5), bf16x3 (2e-3) and fp16x3
+(1e-5 of the sum of magnitudes, rows and columns scaled over 2^-20..2^20); tile
 shapes and the converted-operand paths bitwise equal to the 64x64 result; permutes against
 host loops (1e-14); pair storage pack/unpack against host loops written from the definition."""
 import os

@@ -119,7 +119,8 @@ def test_spectral_function_parity():
     assert np.abs(a2 - a).max() <= 1e-9 * np.abs(a).max()
 
 
-@pytest.mark.parametrize("prec,res_tol,c_tol,qp_tol_ev", [("fp32", 1e-5, 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-5, 1e-3)])
+@pytest.mark.parametrize("prec,res_tol,c_tol,qp_tol_ev", [("fp32", 1e-5, 1e-6, 1e-5), ("bf16x3", 1e-3, 1e-5, 1e-3),
+                                                            ("fp16x3", 1e-5, 1e-6, 1e-5)])
 def test_reduced_precision_against_fp64_oracle(prec, res_tol, c_tol, qp_tol_ev):
     """float32 and bf16x3 contractions (float64 update and C(t)): residual relative Frobenius
     error, C(t) max error over the 200-step tiny trajectory and the QP peak shift in eV, all
@@ -186,7 +187,7 @@ def test_graph_replay_matches_direct_launches():
     assert np.array_equal(a.get_amplitudes()[1], b.get_amplitudes()[1])
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "fp16x3"])
 def test_graph_replay_reduced_precision(prec):
     """Reduced precisions keep converted planes of the constant integral blocks; a graph-mode
     context writes them at init, before any capture, so its replayed steps equal direct
@@ -236,7 +237,8 @@ def test_checkpoint_restart_with_graph_replay():
     assert all(np.array_equal(x, y) for x, y in zip(a.get_amplitudes(), b.get_amplitudes()))
 
 
-@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-6, 1e-6), ("bf16x3", 1e-4, 1e-5)])
+@pytest.mark.parametrize("prec,tol,solve_tol", [("fp64", 1e-10, 1e-11), ("fp32", 1e-6, 1e-6), ("bf16x3", 1e-4, 1e-5),
+                                                   ("fp16x3", 1e-6, 1e-6)])
 def test_ground_state_ccsd(prec, tol, solve_tol):
     """E_N^corr of the tiny workload's N-electron determinant (core_orb = -1) by
     rteom_ground_state against the oracle's Jacobi solution (relative error bound per
@@ -334,7 +336,7 @@ def _formaldehyde_golden():
 
 
 @pytest.mark.parametrize("prec,c_tol,qp_tol_ev", [("fp64", 1e-8, 1e-6), ("fp32", 1e-5, 1e-4),
-                                                   ("bf16x3", 1e-5, 1e-4)])
+                                                   ("bf16x3", 1e-5, 1e-4), ("fp16x3", 1e-5, 1e-4)])
 def test_formaldehyde_trajectory_against_oracle(prec, c_tol, qp_tol_ev):
     """200 time steps of the formaldehyde-shaped core hole (o=8, v=110 per spin, Q=600, L
     scaled by (16/v)^(1/2), dt = 0.025 au, 2 fixed passes per step) in each contraction

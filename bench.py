@@ -21,7 +21,8 @@ sys.path.insert(0, ROOT)
 
 import numpy as np  # noqa: E402
 
-from synthetic import ESCA, ESCA_PAPER, FORMALDEHYDE, TINY, Shape, batched_shapes, draw_system  # noqa: E402
+from synthetic import (ESCA, ESCA_PAPER, FORMALDEHYDE, TINY, ZN_PORPHYRIN, Shape, batched_shapes,  # noqa: E402
+                       draw_system)
 
 # Ladder kernel per precision (the contraction's MFMA instruction family)
 KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands converted to float planes)",
@@ -85,6 +86,12 @@ WORKLOADS = {
                  desc="ESCA-shaped core hole, o=71, v=649 per spin (beta hole: 71/70 occupied, 649/650 "
                       "virtual), Q=2000, L scaled by (16/v)^(1/2), amplitudes seeded N(0,1e-3), one residual "
                       "evaluation plus one step, dt=0.01 au"),
+    # Zn-porphyrin shape (655 orbitals: alpha 95/560, beta 94/561 with the hole), one
+    # fixed-point pass per step (two amplitude sets), split-precision contractions
+    "zn": dict(shape=ZN_PORPHYRIN, cfg=5, dt=0.01, passes=1, steps=10, large=True, seed_amplitudes=1e-3,
+               desc="Zn-porphyrin-shaped core hole, o=95, v=560 per spin (beta hole: 95/94 occupied, 560/561 "
+                    "virtual), Q=3000, L scaled by (16/v)^(1/2), amplitudes seeded N(0,1e-3), one fixed-point "
+                    "pass per step, dt=0.01 au"),
     "esca36": dict(shape=ESCA_PAPER, cfg=3, dt=0.01, passes=2, steps=2, large=True, cpu_sample="formaldehyde",
                    desc="ESCA run of the paper's abstract (71 occupied / 649 virtual spin-orbitals in total): "
                         "o=36, v=324 per spin, Q=2000, L scaled by (16/v)^(1/2), beta hole, dt=0.01 au"),

@@ -129,7 +129,7 @@ struct UpdateOp {
   double* rhs_re = nullptr; double* rhs_im = nullptr;
   double h = 0.0;      // dt / 2
   int mode = 0;        // 0 plain, 1 denominator, 2 Jacobi
-  int start = 0;       // 1: write rhs from x and r first
+  int start = 0;       // 1: form rhs from x and r first (stored when rhs_re is set)
   SpinVectors sv;
   double* delta = nullptr;  // device double, max-reduced (caller zeroes it)
 };

@@ -1215,8 +1215,10 @@ __global__ __launch_bounds__(256) void update_kernel(UpdArgs u) {
       if (u.start) {
         hr = xr - u.h * ri;
         hi = xi + u.h * rr;
-        u.hr_[k] = hr;
-        u.hi_[k] = hi;
+        if (u.hr_) {   // kept for later passes
+          u.hr_[k] = hr;
+          u.hi_[k] = hi;
+        }
       } else {
         hr = u.hr_[k];
         hi = u.hi_[k];

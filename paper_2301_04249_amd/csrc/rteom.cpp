@@ -386,7 +386,8 @@ struct Context {
     }
     const int64_t ns = lay.size();
     X = take(2 * ns);
-    RHS = take(2 * ns);
+    // one fixed pass per step forms the right-hand side in registers: no set for it
+    RHS = opt.fp_fixed_iters == 1 ? nullptr : take(2 * ns);
     R = take(2 * ns);
     if (opt.fp_fixed_iters == 0) Tn = take(2 * ns);
     delta = take(1);
@@ -655,14 +656,20 @@ struct Context {
     for (int s = 0; s < 2; ++s) {
       const int u = 1 - s;
       View r1 = t1(Rs, s);
-      eng.contract("imae,Qme->Qia", tsu(Xs, s), Lov_v, D[s], 1.0, 0);
-      eng.contract("me,imae->ia", fview(fd[u].re, 0, no, no, nv, true), tsu(Xs, s), r1, 1.0, 1);
       for (int64_t i0 = 0; i0 < no; i0 += ci) {
         const int64_t m = std::min<int64_t>(ci, no - i0);
         const size_t mr = arena.mark();
+        // opposite-spin (m, e): the rows' block of the alpha-beta amplitudes (its (m, e)
+        // sum is not one stride, so the engine stages the block, not the whole tensor)
+        View tb = block(tsu(Xs, s), {i0, 0, 0, 0}, {m, no, nv, nv});
+        View Db = block(D[s], {0, i0, 0}, {Q, m, nv}), r1b = block(r1, {i0, 0}, {m, nv});
+        eng.contract("imae,Qme->Qia", tb, Lov_v, Db, 1.0, 0);
+        eng.contract("me,imae->ia", fview(fd[u].re, 0, no, no, nv, true), tb, r1b, 1.0, 1);
+        arena.release(mr);
+        // same-spin (m, e)
         View xt = expand_rows(Xs, s, i0, m);
-        eng.contract("imae,Qme->Qia", xt, Lov_v, block(D[s], {0, i0, 0}, {Q, m, nv}), 1.0, 1);
-        eng.contract("me,imae->ia", fview(fd[s].re, 0, no, no, nv, true), xt, block(r1, {i0, 0}, {m, nv}), 1.0, 1);
+        eng.contract("imae,Qme->Qia", xt, Lov_v, Db, 1.0, 1);
+        eng.contract("me,imae->ia", fview(fd[s].re, 0, no, no, nv, true), xt, r1b, 1.0, 1);
         arena.release(mr);
       }
       eng.add(Lbar[s], Ldvo[s], 1, 0, 0);
@@ -840,17 +847,32 @@ struct Context {
     {
       View Rv = tab(Rs), T = tab(Xs);
       View ta = t1(Xs, 0), tb = t1(Xs, 1);
-      eng.contract("Qai,Qbj->ijab", Lbar[0], Lbar[1], Rv, 1.0, 1);
+      // Products whose operand or result the engine stages (no single stride over a
+      // summed or an output index pair) run over blocks of one occupied index, so that
+      // the staged copies are blocks, not whole o^2 v^2 tensors
+      for (int64_t i0 = 0; i0 < no; i0 += ci) {
+        const int64_t m = std::min<int64_t>(ci, no - i0);
+        eng.contract("Qai,Qbj->ijab", block(Lbar[0], {0, 0, i0}, {Q, nv, m}), Lbar[1],
+                     block(Rv, {i0, 0, 0, 0}, {m, no, nv, nv}), 1.0, 1);
+      }
       eng.contract("ijae,be->ijab", T, Fvv[1], Rv, 1.0, 1);
       eng.contract("ae,ijeb->ijab", Fvv[0], T, Rv, 1.0, 1);
       eng.contract("imab,mj->ijab", T, Foo[1], Rv, -1.0, 1);
-      eng.contract("mi,mjab->ijab", Foo[0], T, Rv, -1.0, 1);
+      for (int64_t j0 = 0; j0 < no; j0 += cj) {
+        const int64_t m = std::min<int64_t>(cj, no - j0);
+        eng.contract("mi,mjab->ijab", Foo[0], block(T, {0, j0, 0, 0}, {no, m, nv, nv}),
+                     block(Rv, {0, j0, 0, 0}, {no, m, nv, nv}), -1.0, 1);
+      }
       const size_t ma = arena.mark();
       View g = with_frac(eng.temp({no, no, no, no}, true), {f_o[0], f_o[1], f_o[0], f_o[1]});
       View Xo = with_frac(eng.temp({no, no, no, no}, true), {f_o[0], f_o[1], f_o[0], f_o[1]});
       View Y = with_frac(eng.temp({no, no, no, nv}, true), {f_o[0], f_o[1], f_o[0], f_v[1]});
       eng.contract("Qmi,Qnj->mnij", Ldoo[0], Ldoo[1], g, 1.0, 0);
-      eng.contract("ijef,menf->ijmn", T, Jv, Xo, 1.0, 0);
+      for (int64_t m0 = 0; m0 < no; m0 += ci) {
+        const int64_t m = std::min<int64_t>(ci, no - m0);
+        eng.contract("ijef,menf->ijmn", T, block(Jv, {m0, 0, 0, 0}, {m, nv, no, nv}),
+                     block(Xo, {0, 0, m0, 0}, {no, no, m, no}), 1.0, 0);
+      }
       eng.contract("mnab,mnij->ijab", T, g, Rv, 1.0, 1);
       // sum_mn tau_mnab Xo_ijmn with tau = t2 + t_ma t_nb
       eng.contract("mnab,ijmn->ijab", T, Xo, Rv, 1.0, 1);
@@ -896,7 +918,7 @@ struct Context {
     u.r_re = R;
     u.r_im = R + lay.size();
     u.rhs_re = RHS;
-    u.rhs_im = RHS + lay.size();
+    u.rhs_im = RHS ? RHS + lay.size() : nullptr;
     u.mode = opt.fp_map;
     u.start = start ? 1 : 0;
     for (int s = 0; s < 2; ++s) {

@@ -11,7 +11,7 @@ exactly PASSES fixed-point passes per step from T(0) = 0, dt = DT, STEPS steps,
 C(t) by the same trapezoid weights (Eq. cum_gf3), then A(omega) and its
 quasi-particle peak (Eqs. cum_gf, cum_gf2) on OMEGAS with damping ETA.
 
-    python tests/golden/make_formaldehyde_trajectory.py [--steps N]
+    python tests/golden/make_formaldehyde_trajectory.py [--steps N] [--fp-map denominator --out FILE]
 
 Output: tests/golden/formaldehyde_trajectory.txt (one line per time point:
 t, Re C, Im C, Re E, Im E; header lines start with '#').  One oracle residual
@@ -50,6 +50,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--steps", type=int, default=STEPS)
     ap.add_argument("--out", default=OUT)
+    ap.add_argument("--fp-map", default="plain", choices=["plain", "denominator"],
+                    help="fixed-point map of the passes (denominator: the diagonal part taken implicitly)")
     args = ap.parse_args(argv)
     sh = FORMALDEHYDE
     eps, chol = draw_system(sh, cfg=CFG, chol_scale=chol_scale(sh.v))
@@ -63,7 +65,7 @@ def main(argv=None):
     ens[0] = ccsd.energy(sysm, t1, t2)
     t0 = time.time()
     for k in range(n):
-        t1, t2, _ = propagate.trapezoid_step(sysm, t1, t2, DT, fixed_iters=PASSES, blocks=blocks)
+        t1, t2, _ = propagate.trapezoid_step(sysm, t1, t2, DT, fixed_iters=PASSES, fp_map=args.fp_map, blocks=blocks)
         ens[k + 1] = ccsd.energy(sysm, t1, t2)
         cum[k + 1] = cum[k] + 0.5j * DT * (ens[k] + ens[k + 1])
         print(f"step {k + 1}/{n}: C = {cum[k + 1]:.12e} ({time.time() - t0:.0f} s)", flush=True)
@@ -77,7 +79,7 @@ def main(argv=None):
         f.write("# Oracle trajectory (tests/golden/make_formaldehyde_trajectory.py): formaldehyde-shaped core hole,\n")
         f.write(f"# o={sh.o} v={sh.v} per spin, Q={sh.nchol}, beta hole at orbital 0, seeds cfg={CFG} sys=0,\n")
         f.write(f"# Cholesky vectors scaled by (16/v)^(1/2) = {chol_scale(sh.v):.17g}; Eq. trapzrule with\n")
-        f.write(f"# {PASSES} fixed-point passes per step, dt={DT}, {n} steps; C(t) by Eq. cum_gf3.\n")
+        f.write(f"# {PASSES} fixed-point passes per step ({args.fp_map} map), dt={DT}, {n} steps; C(t) by Eq. cum_gf3.\n")
         f.write(f"# spectral: omega in [{OMEGA_LO}, {OMEGA_HI}) step {OMEGA_STEP}, eta={ETA}, e_corr=0\n")
         f.write(f"# qp_peak {qp:.15f}\n")
         f.write(f"# a_max {a.max():.15e}\n")

@@ -227,8 +227,10 @@ class HostBackend : public Backend {
       if (u.start) {
         hr = xr - u.h * ri;
         hi = xi + u.h * rr;
-        u.rhs_re[k] = hr;
-        u.rhs_im[k] = hi;
+        if (u.rhs_re) {
+          u.rhs_re[k] = hr;
+          u.rhs_im[k] = hi;
+        }
       } else {
         hr = u.rhs_re[k];
         hi = u.rhs_im[k];

@@ -61,3 +61,32 @@ def test_esca_contract_shape_embedded_parity(capsys):
     assert err < 1e-11
     assert mixed <= 1e-13
     assert e_err <= 1e-11
+
+
+def test_zn_porphyrin_shape_embedded_parity(capsys):
+    """The Zn-porphyrin shape: o=95, v=560 per spin (beta hole: 95/94 occupied, 560/561
+    virtual), Q=3000, fp16x3 contractions with float64 update, one fixed-point pass (two
+    amplitude sets: no right-hand-side set), integral slabs rebuilt per residual.  The tiny
+    system is embedded as a non-interacting part: its residual block against the oracle,
+    every element joining the parts zero, and the energy split."""
+    from synthetic import ZN_PORPHYRIN as ZN
+    print(f"drawing the Zn-porphyrin-shaped system o={ZN.o} v={ZN.v} Q={ZN.nchol}", flush=True)
+    emb = embedding.build(ZN, 5, TINY.o, TINY.v, TINY.nchol)
+    P = rteom.Propagator(emb["eps"], emb["chol"], ZN.o, ZN.o, 0, 1, prec="fp16x3", fixed_iters=1,
+                         tune=False, workspace="torch", max_steps=4, progress=True)
+    del emb["chol"]
+    plan = P.plan()
+    print(f"plan {plan}", flush=True)
+    assert not plan["resident"]
+
+    def run(fn):
+        with capsys.disabled():
+            fn()
+
+    try:
+        err, mixed, e_err = embedding.check_device(P, emb, 1e-5, run)
+    finally:
+        P.close()
+    assert err < 1e-5
+    assert mixed <= 1e-12
+    assert e_err <= 1e-11

@@ -12,7 +12,7 @@ import pytest
 import blocks
 from oracle import ccsd, propagate, reference
 from paper_2301_04249_amd import rteom
-from synthetic import FORMALDEHYDE, Shape, TINY, draw_system
+from synthetic import FORMALDEHYDE, Shape, TINY, batched_shapes, draw_system
 
 pytestmark = pytest.mark.gpu
 
@@ -295,6 +295,41 @@ def test_batch_of_uneven_systems_matches_sequential():
         assert np.array_equal(p.cumulant()[1], q.cumulant()[1])
 
 
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-10), ("fp32", 1e-6)])
+def test_batched_workload_members_against_oracle(prec, tol):
+    """The batched workload as bench.py runs it: 16 uneven core holes (o in [5,20], v in
+    [40,200] per spin, Q = 4v, L scaled by (16/v)^(1/2)), diagonal fixed-point map, 2 passes,
+    every system's step in one graph launch.  C(t) of the members the oracle file holds
+    (tests/golden/make_batched_trajectories.py: those with v <= 125) after 3 steps, against
+    the oracle (FP64 and complex FP32 contractions)."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "batched_trajectories.txt")
+    d = np.loadtxt(path)
+    shapes = batched_shapes(16, cfg=2)
+    ps = []
+    for k, sh in enumerate(shapes):
+        eps, chol = draw_system(sh, cfg=2, sys_id=k, chol_scale=(16.0 / sh.v) ** 0.5)
+        ps.append(_prop(eps, chol, sh.o, sh.o, 0, 1, prec=prec, fixed_iters=2, fp_map=1, graph=True, max_steps=8))
+    batch = rteom.Batch(ps)
+    batch.step(0.025, 3)
+    members = sorted(set(d[:, 0].astype(int)))
+    assert len(members) >= 8
+    worst = 0.0
+    for k in members:
+        rows = d[d[:, 0] == k]
+        sh = shapes[k]
+        assert (rows[0, 1], rows[0, 2], rows[0, 3]) == (sh.o, sh.v, sh.nchol)
+        t, c = ps[k].cumulant()
+        assert np.allclose(t, rows[:, 4])
+        err = np.abs(c - (rows[:, 5] + 1j * rows[:, 6])).max()
+        worst = max(worst, err)
+        print(f"member {k} (o={sh.o}, v={sh.v}): C(t) max abs err {err:.3e}", flush=True)
+    batch.close()
+    for p in ps:
+        p.close()
+    assert worst < tol
+
+
 @pytest.mark.parametrize("slab,block", [(0, 3), (9, 2), (16, 5)])
 def test_blocked_plans_residual_parity(slab, block):
     """Memory plans with the ring intermediates and the expanded same-spin rows in blocks of
@@ -407,3 +442,45 @@ def test_qp_and_satellite_peaks_against_oracle():
     assert peaks.shape == ref.shape and abs(peaks[0, 0] - qp_ref) < 1e-9
     assert np.abs(peaks[:, 0] - ref[:, 0]).max() < 1e-8
     assert np.abs(peaks[:, 1] - ref[:, 1]).max() < 1e-10 * ref[0, 1]
+
+
+def test_formaldehyde_1000_steps():
+    """The formaldehyde-shaped run of 1000 steps (25 au), 2 passes per step with the diagonal
+    (denominator) fixed-point map: two plain passes per step lose stability after ~300 steps
+    at this dt, the denominator map stays bounded.  The FP64 device trajectory against the
+    oracle's over the 30 steps the oracle file holds (tests/golden/make_formaldehyde_trajectory.py
+    --fp-map denominator), then float32, bf16x3 and fp16x3 contractions against that FP64
+    trajectory over all 1000 steps: C(t) max abs error at most 1e-5 of max |C| and the QP peak
+    within 1e-4 eV.  (The oracle's 1000 steps would take about twelve hours on eight host
+    cores; the FP64 device path stands in for it beyond, pinned by its agreement there and by
+    the 200-step plain-map trajectory.)"""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "formaldehyde_denominator_30.txt")
+    d = np.loadtxt(path)
+    c_ref = d[:, 1] + 1j * d[:, 2]
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    omegas = np.arange(-26.0, -14.0, 0.001)
+    runs = {}
+    for prec in ("fp64", "fp32", "bf16x3", "fp16x3"):
+        P = _prop(eps, chol, 8, 8, 0, 1, prec=prec, fixed_iters=2, fp_map=1, tune=False, max_steps=1024)
+        P.step(0.025, 1000)
+        t, c = P.cumulant()
+        _, qp, _ = P.spectral(omegas, 0.01)
+        runs[prec] = (c, qp)
+        P.close()
+        assert np.all(np.isfinite(c))
+        print(f"{prec}: C(25 au) = {c[-1]:.9e}, max |C| {np.abs(c).max():.3f}, QP {qp:.9f} Eh", flush=True)
+    c64, qp64 = runs["fp64"]
+    n = len(c_ref)
+    err = np.abs(c64[:n] - c_ref).max()
+    print(f"fp64 vs oracle over {n - 1} steps: {err:.3e}", flush=True)
+    assert err < 1e-10
+    cmax = np.abs(c64).max()
+    for prec in ("fp32", "bf16x3", "fp16x3"):
+        c, qp = runs[prec]
+        e = np.abs(c - c64).max()
+        shift = (qp - qp64) * HARTREE_EV
+        print(f"{prec} vs fp64 over 1000 steps: C(t) max abs err {e:.3e} (relative to max |C| {e / cmax:.2e}), "
+              f"QP shift {shift:.3e} eV", flush=True)
+        assert e <= 1e-5 * cmax
+        assert abs(shift) < 1e-4

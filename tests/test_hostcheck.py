@@ -41,7 +41,9 @@ def test_residual_and_energy_vs_oracle(case):
     assert abs(P.energy() - ccsd.energy(sysm, t1, t2)) < 1e-12
 
 
-@pytest.mark.parametrize("kw", [dict(fixed_iters=3), dict(tol=1e-12), dict(tol=1e-12, fp_map=1)])
+@pytest.mark.parametrize("kw", [dict(fixed_iters=3), dict(tol=1e-12), dict(tol=1e-12, fp_map=1),
+                                # one pass per step keeps no right-hand-side set
+                                dict(fixed_iters=1), dict(fixed_iters=1, fp_map=1)])
 def test_propagation_vs_oracle(kw):
     eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
     sysm = reference.n_minus_one_reference(eps, chol, 3, 3, 0, 1)

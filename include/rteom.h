@@ -300,11 +300,13 @@ rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask);
 rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops,
                                int64_t* ops);
 
-/* Batch of independent core-hole propagations (Sec. 3: the core-hole simulations "can run
-   simultaneously").  Every context must be in graph mode with fixed passes, on its own
-   stream; the batch borrows them (they must outlive it).  rteom_batch_step advances all of
-   them by n_steps of dt with one graph launch per step: a graph whose independent child
-   nodes are the contexts' captured time steps.  Synchronises on return; then checks every
+/* Batch of independent core-hole propagations (Sec. 3: the propagations of different core
+   holes are independent of each other, so they may run at the same time).  Every context
+   must be in graph mode with fixed passes, on its own stream; the batch borrows them (they
+   must outlive it).  rteom_batch_step advances all of them by n_steps of dt: per step, every
+   context's captured time step is replayed on that context's stream, all members before any
+   wait, so that members run side by side on the device's hardware queues.  Synchronises
+   every member's stream on return; then checks every
    member's non-finite flag (as rteom_step does) and returns NONFINITE naming the first
    member whose E(T) or C(t) turned NaN/Inf (that member enters its failed state). */
 rteom_status rteom_batch_create(rteom_batch** batch, int32_t n, rteom_ctx* const* ctxs);

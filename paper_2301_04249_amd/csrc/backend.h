@@ -254,11 +254,6 @@ class Backend {
   virtual void* end_capture() { return nullptr; }
   virtual void launch_graph(void* exec) { (void)exec; }
   virtual void destroy_graph(void* exec) { (void)exec; }
-  // the captured (not instantiated) graph behind an executable graph
-  virtual void* captured_graph(void* exec) { (void)exec; return nullptr; }
-  // an executable graph whose child nodes are the given captured graphs, with no
-  // dependencies between them (they may run concurrently)
-  virtual void* combine_graphs(void* const* graphs, int n) { (void)graphs; (void)n; return nullptr; }
   virtual void* stream() { return nullptr; }
   // Device memory of a fixed size that needs no allocation (nullptr where there is
   // none); *doubles receives its capacity.  Shared by every caller on the device.

@@ -724,15 +724,18 @@ __device__ inline f16v mma3_32(typename E::vec ah, typename E::vec al, typename 
 // of WM x WN blocks of 32 x 32; a fragment lane holds row (lane % 32) and k
 // (lane / 32) * 8 .. + 7 of its block; accumulator register r of a lane holds row
 // 8 (r / 4) + 4 (lane / 32) + r % 4 and column lane % 32.
-template <typename E, bool AC, bool BC, int WM, int WN>
+// NB: LDS stages (2: the next k tile is staged while the current one is read, one
+// barrier per tile; 1: staged after the current one is read, two barriers per tile,
+// half the LDS, which lets the large tiles keep two work-groups per compute unit)
+template <typename E, bool AC, bool BC, int WM, int WN, int NB>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_bf16x3_split(GemmArgs g) {
   typedef typename E::vec V;
   constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BKH + PADH;
   constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
   constexpr int CA = TM / 64, CB = TN / 64;             // 16-byte chunks per thread and plane
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
-  __shared__ __attribute__((aligned(16))) unsigned short sa[2][PA][TM][LDK];
-  __shared__ __attribute__((aligned(16))) unsigned short sb[2][PB][TN][LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short sa[NB][PA][TM][LDK];
+  __shared__ __attribute__((aligned(16))) unsigned short sb[NB][PB][TN][LDK];
 
   const int tid = threadIdx.x;
   const int lane = tid & 63, wave = tid >> 6;
@@ -832,9 +835,17 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))
             }
           }
       }
-      if (more) stage(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+      if constexpr (NB == 2) {
+        if (more) stage(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+      } else {
+        __syncthreads();   // every wave has read the tile
+        if (more) {
+          stage(0);
+          __syncthreads();
+        }
+      }
     }
     const bool split = g.splitk > 1;
     double* Cr = split ? g.pr + (int64_t)blockIdx.y * g.M * g.N : g.cr + b * g.csb;
@@ -1594,17 +1605,21 @@ void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool 
 
 // Pre-split bf16x3 tile shapes: two LDS buffers of every hi/lo plane must fit
 // 80 KB so that two work-groups share a CU.
-constexpr int split_lds_bytes(bool ac, bool bc, int v) {
-  return 2 * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
+constexpr int split_lds_bytes(bool ac, bool bc, int v, int nb) {
+  return nb * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
 }
 inline bool split_tile_allowed(int v, bool ac, bool bc) {
-  return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v) <= 80 * 1024;
+  return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v, 1) <= 80 * 1024;
 }
 
+// two LDS stages where they fit in 80 KiB (two work-groups per compute unit), else one
 template <typename E, bool AC, bool BC, int WM, int WN, int V>
 bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
-  if constexpr (split_lds_bytes(AC, BC, V) <= 80 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN><<<grid, kThreads, 0, st>>>(g);
+  if constexpr (split_lds_bytes(AC, BC, V, 2) <= 80 * 1024) {
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 2><<<grid, kThreads, 0, st>>>(g);
+    return true;
+  } else if constexpr (split_lds_bytes(AC, BC, V, 1) <= 80 * 1024) {
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 1><<<grid, kThreads, 0, st>>>(g);
     return true;
   }
   return false;
@@ -2203,7 +2218,6 @@ class HipBackend : public Backend {
     hipGraphExec_t exec = nullptr;
     record(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "hipGraphInstantiate");
     graphs_.push_back(graph);
-    children_.push_back({exec, graph});
     return exec;
   }
   void launch_graph(void* exec) override {
@@ -2212,34 +2226,11 @@ class HipBackend : public Backend {
   void destroy_graph(void* exec) override {
     if (exec) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(exec));
   }
-  void* captured_graph(void* exec) override { return child_of(exec); }
-  void* combine_graphs(void* const* graphs, int n) override {
-    hipGraph_t parent = nullptr;
-    record(hipGraphCreate(&parent, 0), "hipGraphCreate");
-    for (int k = 0; k < n; ++k) {
-      hipGraph_t child = static_cast<hipGraph_t>(graphs[k]);
-      if (!child) { set_err("combine_graphs: missing graph"); return nullptr; }
-      hipGraphNode_t node = nullptr;
-      record(hipGraphAddChildGraphNode(&node, parent, nullptr, 0, child), "hipGraphAddChildGraphNode");
-    }
-    hipGraphExec_t exec = nullptr;
-    record(hipGraphInstantiate(&exec, parent, nullptr, nullptr, 0), "hipGraphInstantiate");
-    graphs_.push_back(parent);
-    return exec;
-  }
-
 
  private:
   struct Timed { hipEvent_t a, b; int ph; };
-  struct Child { void* exec; hipGraph_t graph; };
   std::vector<hipGraph_t> graphs_;
-  std::vector<Child> children_;
   bool capturing_ = false;
-  hipGraph_t child_of(void* exec) const {
-    for (const auto& c : children_)
-      if (c.exec == exec) return c.graph;
-    return nullptr;
-  }
   hipStream_t stream_;
   std::string err_;
   unsigned mask_ = 0;

@@ -1770,8 +1770,6 @@ rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double
 
 struct rteom_batch {
   std::vector<rteom_ctx*> ctxs;
-  void* exec = nullptr;
-  double dt = 0.0;
   std::string err;
 };
 
@@ -1799,27 +1797,21 @@ rteom_status rteom_batch_step(rteom_batch* b, double dt, int32_t n_steps) {
   rteom_status st = guarded(lead, [&] {
     for (rteom_ctx* x : b->ctxs)
       if (x->c.nsteps + n_steps > x->c.opt.max_steps) throw Error(RTEOM_ERR_STATE, "C(t) history would overflow");
-    if (!b->exec || b->dt != dt) {
-      std::vector<void*> graphs;
-      for (rteom_ctx* x : b->ctxs) {
-        void* e = x->c.graph_for(dt);
-        if (!e) throw Error(RTEOM_ERR_STATE, "graph capture unavailable (null stream?)");
-        graphs.push_back(x->c.be->captured_graph(e));
-        x->c.be->sync();
-      }
-      if (b->exec) lead->c.be->destroy_graph(b->exec);
-      b->exec = lead->c.be->combine_graphs(graphs.data(), (int)graphs.size());
-      if (!b->exec) throw Error(RTEOM_ERR_HIP, "could not build the batch graph");
-      b->dt = dt;
-    }
+    // Every member's captured step is replayed on the member's own stream, all members
+    // before any wait: the streams map onto the device's hardware queues, so the small
+    // products of different members run side by side.  (One parent graph holding every
+    // member's step as a child node ran them one after another on this runtime.)
+    for (rteom_ctx* x : b->ctxs)
+      if (!x->c.graph_for(dt)) throw Error(RTEOM_ERR_STATE, "graph capture unavailable (null stream?)");
+    for (rteom_ctx* x : b->ctxs) x->c.be->sync();
     for (int32_t k = 0; k < n_steps; ++k) {
-      lead->c.be->launch_graph(b->exec);
       for (rteom_ctx* x : b->ctxs) {
+        x->c.be->launch_graph(x->c.graph_for(dt));
         ++x->c.nsteps;
         x->c.times.push_back(x->c.times.back() + dt);
       }
     }
-    lead->c.be->sync();
+    for (rteom_ctx* x : b->ctxs) x->c.be->sync();
     for (size_t k = 0; k < b->ctxs.size(); ++k) {
       Context& x = b->ctxs[k]->c;
       try {
@@ -1837,7 +1829,6 @@ rteom_status rteom_batch_step(rteom_batch* b, double dt, int32_t n_steps) {
 
 rteom_status rteom_batch_free(rteom_batch* b) {
   if (!b) return RTEOM_OK;
-  if (b->exec && !b->ctxs.empty()) b->ctxs[0]->c.be->destroy_graph(b->exec);
   delete b;
   return RTEOM_OK;
 }

@@ -416,7 +416,7 @@ class Propagator:
 
 
 class Batch:
-    """Several propagations advanced together, one graph launch per time step (rteom_batch_*)."""
+    """Several propagations advanced together, each one's captured step replayed on its own stream (rteom_batch_*)."""
 
     def __init__(self, props):
         self.props = list(props)

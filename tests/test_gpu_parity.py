@@ -280,7 +280,8 @@ def test_anderson_acceleration_on_device():
 
 
 def test_batch_of_uneven_systems_matches_sequential():
-    """Three uneven core-hole systems in one graph launch per step equal their separate runs."""
+    """Three uneven core-hole systems advanced as a batch (each step replayed on its own stream) equal
+    their separate runs."""
     shapes = [Shape(3, 9, 20), Shape(4, 14, 40), Shape(5, 11, 30)]
     seq, bat = [], []
     for k, sh in enumerate(shapes):
@@ -299,7 +300,7 @@ def test_batch_of_uneven_systems_matches_sequential():
 def test_batched_workload_members_against_oracle(prec, tol):
     """The batched workload as bench.py runs it: 16 uneven core holes (o in [5,20], v in
     [40,200] per spin, Q = 4v, L scaled by (16/v)^(1/2)), diagonal fixed-point map, 2 passes,
-    every system's step in one graph launch.  C(t) of the members the oracle file holds
+    every system's captured step replayed on its own stream.  C(t) of the members the oracle file holds
     (tests/golden/make_batched_trajectories.py: those with v <= 125) after 3 steps, against
     the oracle (FP64 and complex FP32 contractions)."""
     import os

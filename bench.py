@@ -36,8 +36,8 @@ KERNEL_NAME = {"fp64": "gemm_mfma<double>", "fp32": "gemm_mfma<float> (operands 
 TRAFFIC = {
     # profiles/gemm_mfma_ladder_esca_fp64.md: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, mean of the
     # alpha-beta and same-spin ladder launches
-    ("esca", "fp64"): (1.030e12, "profiles/gemm_mfma_ladder_esca71_fp64.md: FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
-                                 "mean of the 162 counted ladder launches"),
+    ("esca", "fp64"): (2.332e12, "profiles/gemm_mfma_ladder_esca71_fp64.md: FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
+                                 "mean of the 82 counted ladder launches (integral slabs of 16)"),
     ("esca36", "fp64"): (7.94e11, "profiles/gemm_mfma_ladder_esca_fp64.md (o=36, v=324; kernel unchanged since)"),
 }
 

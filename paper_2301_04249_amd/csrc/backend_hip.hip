@@ -724,11 +724,13 @@ __device__ inline f16v mma3_32(typename E::vec ah, typename E::vec al, typename 
 // of WM x WN blocks of 32 x 32; a fragment lane holds row (lane % 32) and k
 // (lane / 32) * 8 .. + 7 of its block; accumulator register r of a lane holds row
 // 8 (r / 4) + 4 (lane / 32) + r % 4 and column lane % 32.
-// NB: LDS stages (2: the next k tile is staged while the current one is read, one
-// barrier per tile; 1: staged after the current one is read, two barriers per tile,
-// half the LDS, which lets the large tiles keep two work-groups per compute unit)
-template <typename E, bool AC, bool BC, int WM, int WN, int NB>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void gemm_bf16x3_split(GemmArgs g) {
+// NB: LDS stages (the next k tile is always fetched into registers while the current
+// one is read; 2: staged into the other stage, one barrier per tile; 1: staged after
+// every wave has read the current one, two barriers per tile).
+// OCC: waves per SIMD the registers are sized for (1 lets the 128 x 128 tiles keep
+// their accumulators, operands and prefetch in registers: 512 per lane, no spills).
+template <typename E, bool AC, bool BC, int WM, int WN, int NB, int OCC>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void gemm_bf16x3_split(GemmArgs g) {
   typedef typename E::vec V;
   constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BKH + PADH;
   constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
@@ -1609,17 +1611,24 @@ constexpr int split_lds_bytes(bool ac, bool bc, int v, int nb) {
   return nb * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
 }
 inline bool split_tile_allowed(int v, bool ac, bool bc) {
-  return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v, 1) <= 80 * 1024;
+  return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v, 2) <= 160 * 1024;
 }
 
-// two LDS stages where they fit in 80 KiB (two work-groups per compute unit), else one
+// Two LDS stages within 80 KiB: two work-groups per compute unit (two waves per SIMD).
+// Larger tiles: complex x complex keeps two stages in up to the 160 KiB of a compute
+// unit, one work-group with the whole register file per wave; the others keep two
+// work-groups per compute unit with one stage.  (Measured on the ring and ladder
+// shapes of the o=71, v=650 residual.)
 template <typename E, bool AC, bool BC, int WM, int WN, int V>
 bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
   if constexpr (split_lds_bytes(AC, BC, V, 2) <= 80 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN, 2><<<grid, kThreads, 0, st>>>(g);
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 2><<<grid, kThreads, 0, st>>>(g);
     return true;
-  } else if constexpr (split_lds_bytes(AC, BC, V, 1) <= 80 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN, 1><<<grid, kThreads, 0, st>>>(g);
+  } else if constexpr (AC && BC && split_lds_bytes(AC, BC, V, 2) <= 160 * 1024) {
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 1><<<grid, kThreads, 0, st>>>(g);
+    return true;
+  } else if constexpr (!(AC && BC) && split_lds_bytes(AC, BC, V, 1) <= 80 * 1024) {
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 1, 2><<<grid, kThreads, 0, st>>>(g);
     return true;
   }
   return false;
@@ -2026,6 +2035,13 @@ class HipBackend : public Backend {
     auto it = tuned_.find(key);
     if (it != tuned_.end()) return it->second;
     if (!tuning_ || capturing_) {
+      if (presplit && op.prec >= 2 && g.kchunk >= 4096) {
+        // split products (measured on the o=71, v=650 residual's shapes): complex x
+        // complex and products with one short side run best on 128 x 128 tiles, the
+        // other mixed ones on 64 x 128
+        const int v = (ac && bc) || std::min(op.M, op.N) <= 8192 ? 3 : 1;
+        if (split_tile_allowed(v, ac, bc)) return v;
+      }
       int best = cand[0];
       double bt = rule_time(g, cand[0], op.batch, ac, bc);
       for (int i = 1; i < nc && g.kchunk >= 4096; ++i) {

@@ -274,6 +274,10 @@ def main(argv=None):
                     help="seconds for warm-up plus timed steps of the large workloads (caps both)")
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16x3", "fp16x3"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tune", action="store_true",
+                    help="time the GEMM tile shapes of every new product (default for the small workloads)")
+    ap.add_argument("--tile-cache", default=None, metavar="PATH",
+                    help="load timed tile choices from PATH if it exists; with --tune, save them there afterwards")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (HBM counter calibration) and exit")
     args = ap.parse_args(argv)
@@ -312,7 +316,9 @@ def main(argv=None):
     def run(graph):
         P = rteom.Propagator(eps, chol, shape.o, shape.o, 0, 1, prec=args.prec, fixed_iters=work["passes"],
                              workspace="torch", max_steps=req_steps + req_warmup + 4, graph=graph,
-                             tune=not large, progress=large)
+                             tune=args.tune or not large, progress=large)
+        if args.tile_cache and os.path.exists(args.tile_cache):
+            P.load_tiles(args.tile_cache)
         plan = P.plan()
         print(f"[bench] {'graph' if graph else 'direct'} launches: context ready, plan {plan}", file=sys.stderr,
               flush=True)
@@ -352,6 +358,8 @@ def main(argv=None):
         t1 = time.perf_counter()
         print(f"[bench] timed {steps} steps: {(t1 - t0) * 1e3 / steps:.2f} ms/step", file=sys.stderr, flush=True)
         stats = {ph: P.phase_stats(ph) for ph in rteom.PHASES}
+        if args.tune and args.tile_cache:
+            P.save_tiles(args.tile_cache)
         return P, iters, t0, t1, stats, steps, warmup
 
     # Timed region 1 gives the value.  Small workloads replay each step as a
@@ -397,7 +405,9 @@ def main(argv=None):
     config = {"workload": work["desc"], "chol_scale": scale, "passes_per_step": work["passes"],
               "residuals_timed": n_res, "steps_requested": req_steps, "warmup_requested": req_warmup,
               "launch": launch, "flops_per_residual": flops_res, "exec_flops_per_residual": plan["exec_flops"],
-              "s_per_residual": (t1 - t0) / n_res, "memory_plan": plan}
+              "s_per_residual": (t1 - t0) / n_res, "memory_plan": plan,
+              "tile_choice": ("timed" if args.tune or not large else "rule")
+                             + (f", cache {args.tile_cache}" if args.tile_cache else "")}
     if ms_direct is not None:
         config["ms_per_step_direct_launch"] = round(ms_direct, 4)
     if large:

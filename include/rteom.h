@@ -300,6 +300,19 @@ rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask);
 rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops,
                                int64_t* ops);
 
+/* Persisted tile choices.  A context created with tune = 1 times the tile shapes of every
+   new GEMM signature once and keeps the fastest; rteom_tile_cache_save writes those
+   choices to a text file (a header "rteom-tiles 1 <gfx target>", then one line per
+   signature: precision (+8 for converted operands), M, N, K, batch, A complex, B complex,
+   A k-contiguous, B k-contiguous, split-K factor, tile shape).  rteom_tile_cache_load adds
+   a file's choices to a context (later ones replace earlier ones for a signature); they
+   are used before timing or the rule, with tune = 0 as well.  Tile shapes change the work
+   assignment only, never the arithmetic.  Errors: ARG for a NULL argument, a file that
+   cannot be opened or is malformed, another device target, or a tile shape that is not
+   built for its signature (nothing is loaded then).  The file is the caller's. */
+rteom_status rteom_tile_cache_save(rteom_ctx* ctx, const char* path);
+rteom_status rteom_tile_cache_load(rteom_ctx* ctx, const char* path);
+
 /* Batch of independent core-hole propagations (Sec. 3: the propagations of different core
    holes are independent of each other, so they may run at the same time).  Every context
    must be in graph mode with fixed passes, on its own stream; the batch borrows them (they

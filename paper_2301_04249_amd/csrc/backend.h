@@ -210,6 +210,19 @@ class Backend {
   // 3: 128x128, 4: 64x128 and 5: 128x64 with eight waves) where the operand
   // types and precision allow it (else 64x64); -1 = automatic.
   virtual void force_tile(int v) { (void)v; }
+  // Timed tile choices, kTileKey + 1 values per entry (the GEMM signature, then the tile
+  // shape): tile_table copies up to max entries into rows and returns how many there are;
+  // load_tile_table adds entries (a later entry for the same signature replaces it) and
+  // rejects a table whose tile shape is not built for its signature.
+  static constexpr int kTileKey = 10;
+  virtual int64_t tile_table(int64_t* rows, int64_t max) const { (void)rows; (void)max; return 0; }
+  virtual bool load_tile_table(const int64_t* rows, int64_t n, std::string* err) {
+    (void)rows;
+    if (n > 0 && err) *err = "this backend keeps no tile choices";
+    return n == 0;
+  }
+  // the device's architecture name (tile choices are only valid on it)
+  virtual std::string device_arch() const { return "host"; }
   // total milliseconds and operation count of the profiled phase since the last call
   virtual double phase_ms(int ph, int64_t* ops) { (void)ph; if (ops) *ops = 0; return 0.0; }
  protected:

@@ -729,12 +729,16 @@ __device__ inline f16v mma3_32(typename E::vec ah, typename E::vec al, typename 
 // every wave has read the current one, two barriers per tile).
 // OCC: waves per SIMD the registers are sized for (1 lets the 128 x 128 tiles keep
 // their accumulators, operands and prefetch in registers: 512 per lane, no spills).
-template <typename E, bool AC, bool BC, int WM, int WN, int NB, int OCC>
+// BK: k per LDS stage (32 in every launched shape: with 16 the mixed 128 x 128 tile spills
+// less but runs 2.8x slower).
+template <typename E, bool AC, bool BC, int WM, int WN, int NB, int OCC, int BK>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8))) void gemm_bf16x3_split(GemmArgs g) {
   typedef typename E::vec V;
-  constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BKH + PADH;
+  constexpr int TM = 64 * WM, TN = 64 * WN, LDK = BK + PADH;
   constexpr int PA = AC ? 4 : 2, PB = BC ? 4 : 2;      // hi, lo of each real plane
-  constexpr int CA = TM / 64, CB = TN / 64;             // 16-byte chunks per thread and plane
+  constexpr int CPR = BK / 8, RPP = kThreads / CPR;     // 16-byte chunks per row, rows per pass
+  static_assert(TM % RPP == 0 && TN % RPP == 0, "tile rows must fill whole passes");
+  constexpr int CA = TM / RPP, CB = TN / RPP;           // 16-byte chunks per thread and plane
   typedef unsigned int u4 __attribute__((ext_vector_type(4)));
   __shared__ __attribute__((aligned(16))) unsigned short sa[NB][PA][TM][LDK];
   __shared__ __attribute__((aligned(16))) unsigned short sb[NB][PB][TN][LDK];
@@ -745,7 +749,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8
   int64_t tm, tn;
   tile_coords(g, blockIdx.x, tm, tn);
   const int64_t m0 = tm * TM, n0 = tn * TN;
-  const int crow = tid >> 2, cofs = (tid & 3) * 8;      // 64 rows x 4 chunks of 8 k per pass
+  const int crow = tid / CPR, cofs = (tid % CPR) * 8;  // RPP rows x CPR chunks of 8 k per pass
   int64_t kbeg = 0, kend = g.sld, b0 = blockIdx.y, bstep = gridDim.y;
   if (g.splitk > 1) {
     kbeg = (int64_t)blockIdx.y * g.kchunk;
@@ -770,14 +774,14 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8
     auto fetch = [&](int64_t k0) {
 #pragma unroll
       for (int c = 0; c < CA; ++c) {
-        const int64_t gm = m0 + crow + 64 * c;
+        const int64_t gm = m0 + crow + RPP * c;
 #pragma unroll
         for (int p = 0; p < PA; ++p)
           ra[p][c] = gm < g.M ? *reinterpret_cast<const u4*>(g.sa[p] + ao + gm * g.sld + k0 + cofs) : u4{0, 0, 0, 0};
       }
 #pragma unroll
       for (int c = 0; c < CB; ++c) {
-        const int64_t gn = n0 + crow + 64 * c;
+        const int64_t gn = n0 + crow + RPP * c;
 #pragma unroll
         for (int p = 0; p < PB; ++p)
           rb[p][c] = gn < g.N ? *reinterpret_cast<const u4*>(g.sb[p] + bo + gn * g.sld + k0 + cofs) : u4{0, 0, 0, 0};
@@ -787,11 +791,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8
 #pragma unroll
       for (int c = 0; c < CA; ++c)
 #pragma unroll
-        for (int p = 0; p < PA; ++p) *reinterpret_cast<u4*>(&sa[buf][p][crow + 64 * c][cofs]) = ra[p][c];
+        for (int p = 0; p < PA; ++p) *reinterpret_cast<u4*>(&sa[buf][p][crow + RPP * c][cofs]) = ra[p][c];
 #pragma unroll
       for (int c = 0; c < CB; ++c)
 #pragma unroll
-        for (int p = 0; p < PB; ++p) *reinterpret_cast<u4*>(&sb[buf][p][crow + 64 * c][cofs]) = rb[p][c];
+        for (int p = 0; p < PB; ++p) *reinterpret_cast<u4*>(&sb[buf][p][crow + RPP * c][cofs]) = rb[p][c];
     };
     if (kbeg < kend) {
       fetch(kbeg);
@@ -800,11 +804,11 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(OCC, 8
     __syncthreads();
     int buf = 0;
     const int l32 = lane & 31, kh = (lane >> 5) * 8;
-    for (int64_t k0 = kbeg; k0 < kend; k0 += BKH) {
-      const bool more = k0 + BKH < kend;
-      if (more) fetch(k0 + BKH);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+      const bool more = k0 + BK < kend;
+      if (more) fetch(k0 + BK);
 #pragma unroll
-      for (int ks = 0; ks < BKH / 16; ++ks) {
+      for (int ks = 0; ks < BK / 16; ++ks) {
         const int kk = ks * 16 + kh;
         V xrh[WM], xrl[WM], xih[WM], xil[WM], yrh[WN], yrl[WN], yih[WN], yil[WN];
 #pragma unroll
@@ -1607,8 +1611,8 @@ void launch_bf16x3(dim3 grid, hipStream_t st, const GemmArgs& g, bool akc, bool 
 
 // Pre-split bf16x3 tile shapes: two LDS buffers of every hi/lo plane must fit
 // 80 KB so that two work-groups share a CU.
-constexpr int split_lds_bytes(bool ac, bool bc, int v, int nb) {
-  return nb * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (BKH + PADH) * 2;
+constexpr int split_lds_bytes(bool ac, bool bc, int v, int nb, int bk = BKH) {
+  return nb * ((ac ? 4 : 2) * kTileM[v] + (bc ? 4 : 2) * kTileN[v]) * (bk + PADH) * 2;
 }
 inline bool split_tile_allowed(int v, bool ac, bool bc) {
   return v >= 0 && v < 4 && split_lds_bytes(ac, bc, v, 2) <= 160 * 1024;
@@ -1622,13 +1626,13 @@ inline bool split_tile_allowed(int v, bool ac, bool bc) {
 template <typename E, bool AC, bool BC, int WM, int WN, int V>
 bool launch_split_tile(dim3 grid, hipStream_t st, const GemmArgs& g) {
   if constexpr (split_lds_bytes(AC, BC, V, 2) <= 80 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 2><<<grid, kThreads, 0, st>>>(g);
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 2, BKH><<<grid, kThreads, 0, st>>>(g);
     return true;
   } else if constexpr (AC && BC && split_lds_bytes(AC, BC, V, 2) <= 160 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 1><<<grid, kThreads, 0, st>>>(g);
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 2, 1, BKH><<<grid, kThreads, 0, st>>>(g);
     return true;
   } else if constexpr (!(AC && BC) && split_lds_bytes(AC, BC, V, 1) <= 80 * 1024) {
-    gemm_bf16x3_split<E, AC, BC, WM, WN, 1, 2><<<grid, kThreads, 0, st>>>(g);
+    gemm_bf16x3_split<E, AC, BC, WM, WN, 1, 2, BKH><<<grid, kThreads, 0, st>>>(g);
     return true;
   }
   return false;
@@ -1993,6 +1997,48 @@ class HipBackend : public Backend {
   void set_tuning(int on) override { tuning_ = on != 0; }
   void force_tile(int v) override { force_ = v; }
 
+  int64_t tile_table(int64_t* rows, int64_t max) const override {
+    int64_t n = 0;
+    for (const auto& kv : tuned_) {
+      if (rows && n < max) {
+        for (int k = 0; k < kTileKey; ++k) rows[n * (kTileKey + 1) + k] = kv.first[k];
+        rows[n * (kTileKey + 1) + kTileKey] = kv.second;
+      }
+      ++n;
+    }
+    return n;
+  }
+  bool load_tile_table(const int64_t* rows, int64_t n, std::string* err) override {
+    std::map<std::array<int64_t, 10>, int> add;
+    for (int64_t i = 0; i < n; ++i) {
+      const int64_t* r = rows + i * (kTileKey + 1);
+      std::array<int64_t, 10> key;
+      for (int k = 0; k < kTileKey; ++k) key[k] = r[k];
+      // key: precision (+8 when the operands are converted first), M, N, K, batch,
+      // A complex, B complex, A k-contiguous, B k-contiguous, split-K factor
+      const int64_t pr = key[0] & 7, tile = r[kTileKey];
+      const bool presplit = key[0] >= 8, ac = key[5] != 0, bc = key[6] != 0;
+      const bool ok = key[0] >= 0 && key[0] < 16 && pr <= 3 && key[1] > 0 && key[2] > 0 && key[3] > 0 && key[4] > 0 &&
+                      key[9] > 0 && tile >= 0 && tile < kTiles &&
+                      ((presplit && pr >= 2) ? split_tile_allowed((int)tile, ac, bc)
+                                             : tile_allowed((int)tile, (int)pr, ac, bc));
+      if (!ok) {
+        if (err) *err = "tile table entry " + std::to_string(i) + " is not a built tile shape for its product";
+        return false;
+      }
+      add[key] = (int)tile;
+    }
+    for (const auto& kv : add) tuned_[kv.first] = kv.second;
+    return true;
+  }
+  std::string device_arch() const override {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) return "unknown";
+    std::string a = prop.gcnArchName;
+    return a.substr(0, a.find(':'));   // the target without its feature flags
+  }
+
   // Grid of tile shape v (tiles x split or batch); false on overflow.
   bool shape_grid(GemmArgs& g, int v, int64_t batch, dim3* grid) {
     g.tiles_m = (g.M + kTileM[v] - 1) / kTileM[v];
@@ -2035,10 +2081,10 @@ class HipBackend : public Backend {
     auto it = tuned_.find(key);
     if (it != tuned_.end()) return it->second;
     if (!tuning_ || capturing_) {
-      if (presplit && op.prec >= 2 && g.kchunk >= 4096) {
-        // split products (measured on the o=71, v=650 residual's shapes): complex x
-        // complex and products with one short side run best on 128 x 128 tiles, the
-        // other mixed ones on 64 x 128
+      if (presplit && op.prec >= 2 && g.kchunk >= 1024) {
+        // split products (timed on the o=71, v=650 residual's shapes, sums of 2000
+        // and more): complex x complex and products with one short side run best on
+        // 128 x 128 tiles, the other mixed ones on 64 x 128
         const int v = (ac && bc) || std::min(op.M, op.N) <= 8192 ? 3 : 1;
         if (split_tile_allowed(v, ac, bc)) return v;
       }

@@ -1755,6 +1755,62 @@ rteom_status rteom_profile(rteom_ctx* ctx, uint32_t phase_mask) {
   return RTEOM_OK;
 }
 
+// Tile-choice cache file: a header line "rteom-tiles 1 <arch>", then one line per timed
+// GEMM signature: the ten key values and the tile shape, as decimal integers.
+static const char kTileMagic[] = "rteom-tiles";
+
+rteom_status rteom_tile_cache_save(rteom_ctx* ctx, const char* path) {
+  if (!ctx || !path) { g_last_error = "NULL argument"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  return guarded(ctx, [&] {
+    constexpr int w = rteom::Backend::kTileKey + 1;
+    const int64_t n = c.be->tile_table(nullptr, 0);
+    std::vector<int64_t> rows((size_t)std::max<int64_t>(1, n) * w);
+    c.be->tile_table(rows.data(), n);
+    std::FILE* f = std::fopen(path, "w");
+    if (!f) throw Error(RTEOM_ERR_ARG, std::string("cannot write ") + path);
+    bool ok = std::fprintf(f, "%s 1 %s\n", kTileMagic, c.be->device_arch().c_str()) > 0;
+    for (int64_t i = 0; i < n && ok; ++i) {
+      for (int k = 0; k < w && ok; ++k)
+        ok = std::fprintf(f, k + 1 < w ? "%lld " : "%lld\n", (long long)rows[(size_t)(i * w + k)]) > 0;
+    }
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) throw Error(RTEOM_ERR_ARG, std::string("write error on ") + path);
+  });
+}
+
+rteom_status rteom_tile_cache_load(rteom_ctx* ctx, const char* path) {
+  if (!ctx || !path) { g_last_error = "NULL argument"; return RTEOM_ERR_ARG; }
+  Context& c = ctx->c;
+  return guarded(ctx, [&] {
+    constexpr int w = rteom::Backend::kTileKey + 1;
+    std::FILE* f = std::fopen(path, "r");
+    if (!f) throw Error(RTEOM_ERR_ARG, std::string("cannot read ") + path);
+    char magic[32] = {0}, arch[128] = {0};
+    int version = 0;
+    const int got = std::fscanf(f, "%31s %d %127s", magic, &version, arch);
+    if (got != 3 || std::strcmp(magic, kTileMagic) != 0 || version != 1) {
+      std::fclose(f);
+      throw Error(RTEOM_ERR_ARG, std::string(path) + " is not a tile cache file");
+    }
+    if (c.be->device_arch() != arch) {
+      std::fclose(f);
+      throw Error(RTEOM_ERR_ARG, std::string(path) + " holds tile choices for " + arch + ", not for " +
+                                     c.be->device_arch());
+    }
+    std::vector<int64_t> rows;
+    long long v = 0;
+    int r;
+    while ((r = std::fscanf(f, "%lld", &v)) == 1) rows.push_back(v);
+    const bool eof = std::feof(f) != 0;
+    std::fclose(f);
+    if (r != EOF || !eof || rows.size() % w != 0)
+      throw Error(RTEOM_ERR_ARG, std::string(path) + ": malformed tile cache entries");
+    std::string m;
+    if (!c.be->load_tile_table(rows.data(), (int64_t)(rows.size() / w), &m)) throw Error(RTEOM_ERR_ARG, path + (": " + m));
+  });
+}
+
 rteom_status rteom_phase_stats(rteom_ctx* ctx, int32_t phase, double* ms, double* flops, int64_t* ops) {
   if (!ctx) { g_last_error = "NULL context"; return RTEOM_ERR_ARG; }
   if (phase < 0 || phase >= rteom::kNumPhases) { ctx->c.err = "bad phase"; return RTEOM_ERR_ARG; }

@@ -23,7 +23,8 @@ PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "fp16x3": 3}
 SYMBOLS = (
     "rteom_default_options", "rteom_workspace_query", "rteom_init", "rteom_step", "rteom_cumulant",
     "rteom_spectral", "rteom_spectral_noalloc", "rteom_spectral_peaks", "rteom_ground_state", "rteom_checkpoint", "rteom_restore", "rteom_dims", "rteom_set_amplitudes", "rteom_get_amplitudes", "rteom_residual", "rteom_energy",
-    "rteom_residual_flops", "rteom_plan_info", "rteom_device_sets", "rteom_profile", "rteom_phase_stats", "rteom_batch_create",
+    "rteom_residual_flops", "rteom_plan_info", "rteom_device_sets", "rteom_profile", "rteom_phase_stats",
+    "rteom_tile_cache_save", "rteom_tile_cache_load", "rteom_batch_create",
     "rteom_batch_step",
     "rteom_batch_free", "rteom_free", "rteom_last_error",
 )
@@ -106,6 +107,8 @@ def load(path: str = LIB_PATH):
                                     c.POINTER(c.c_int64), _dp, c.POINTER(c.c_size_t)]
     lib.rteom_profile.argtypes = [c.c_void_p, c.c_uint32]
     lib.rteom_phase_stats.argtypes = [c.c_void_p, c.c_int32, _dp, _dp, c.POINTER(c.c_int64)]
+    lib.rteom_tile_cache_save.argtypes = [c.c_void_p, c.c_char_p]
+    lib.rteom_tile_cache_load.argtypes = [c.c_void_p, c.c_char_p]
     lib.rteom_batch_create.argtypes = [c.POINTER(c.c_void_p), c.c_int32, c.POINTER(c.c_void_p)]
     lib.rteom_batch_step.argtypes = [c.c_void_p, c.c_double, c.c_int32]
     lib.rteom_batch_free.argtypes = [c.c_void_p]
@@ -402,6 +405,14 @@ class Propagator:
                                         ctypes.byref(n))
         self._check(st, self.h)
         return ms.value, n.value, fl.value
+
+    def save_tiles(self, path):
+        """Write the context's timed tile choices to a file (rteom_tile_cache_save)."""
+        self._check(self.lib.rteom_tile_cache_save(self.h, os.fsencode(path)), self.h)
+
+    def load_tiles(self, path):
+        """Add a file's tile choices to the context (rteom_tile_cache_load)."""
+        self._check(self.lib.rteom_tile_cache_load(self.h, os.fsencode(path)), self.h)
 
     def close(self):
         if getattr(self, "h", None):

@@ -485,3 +485,29 @@ def test_formaldehyde_1000_steps():
               f"QP shift {shift:.3e} eV", flush=True)
         assert e <= 1e-5 * cmax
         assert abs(shift) < 1e-4
+
+
+def test_tile_cache_round_trip(tmp_path):
+    """Timed tile choices persist: a tuned formaldehyde-shaped FP32 context saves its
+    choices, an untuned context loads them (its own save then lists the same entries) and
+    steps to bitwise the same C(t); a tile shape that is not built for its product is
+    refused."""
+    eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
+    a = _prop(eps, chol, 8, 8, 0, 1, prec="fp32", fixed_iters=2, tune=True)
+    a.step(0.025, 2)
+    pa, pb = tmp_path / "a.txt", tmp_path / "b.txt"
+    a.save_tiles(pa)
+    lines = pa.read_text().splitlines()
+    assert lines[0].startswith("rteom-tiles 1 gfx") and len(lines) > 1
+    b = _prop(eps, chol, 8, 8, 0, 1, prec="fp32", fixed_iters=2, tune=False)
+    b.load_tiles(pa)
+    b.step(0.025, 2)
+    b.save_tiles(pb)
+    assert sorted(pb.read_text().splitlines()[1:]) == sorted(lines[1:])
+    assert np.array_equal(a.cumulant()[1], b.cumulant()[1])
+    # tile 3 (128 x 128) is not built for a float64 complex x complex product
+    pa.write_text(lines[0] + "\n0 640 640 640 1 1 1 1 1 1 3\n")
+    with pytest.raises(rteom.RteomError):
+        b.load_tiles(pa)
+    a.close()
+    b.close()

@@ -306,3 +306,32 @@ def test_spectral_peaks_on_the_host_engine():
     ref = propagate.spectral_peaks(omegas, a_ref, 5)
     assert peaks.shape == ref.shape and len(peaks) >= 2
     assert np.abs(peaks - ref).max() < 1e-9
+
+
+def test_tile_cache_files(tmp_path):
+    """rteom_tile_cache_save / _load: the file format and its errors.  The host engine keeps
+    no timed tile choices, so its file is the header alone; a file for another device
+    target, a foreign or malformed file, and entries the backend cannot use are refused."""
+    eps, chol = draw_system(Shape(3, 5, 12), cfg=0)
+    P = rteom.Propagator(eps, chol, 3, 3, 0, 1, lib_path=LIB)
+    path = tmp_path / "tiles.txt"
+    P.save_tiles(path)
+    assert path.read_text() == "rteom-tiles 1 host\n"
+    P.load_tiles(path)
+    bad = {
+        "other target": "rteom-tiles 1 gfx942\n",
+        "foreign": "something else\n",
+        "version": "rteom-tiles 2 host\n",
+        "ragged": "rteom-tiles 1 host\n0 64 64 64 1 0 0 1 1 1\n",
+        "not a number": "rteom-tiles 1 host\n0 64 64 64 1 0 0 1 1 1 x\n",
+        "entries on the host": "rteom-tiles 1 host\n0 64 64 64 1 0 0 1 1 1 0\n",
+    }
+    for what, text in bad.items():
+        path.write_text(text)
+        with pytest.raises(rteom.RteomError) as e:
+            P.load_tiles(path)
+        assert e.value.status == 1, what
+    with pytest.raises(rteom.RteomError):
+        P.load_tiles(tmp_path / "missing.txt")
+    P.step(0.025, 1)       # the context stays usable
+    P.close()

@@ -302,7 +302,8 @@ def test_batched_workload_members_against_oracle(prec, tol):
     [40,200] per spin, Q = 4v, L scaled by (16/v)^(1/2)), diagonal fixed-point map, 2 passes,
     every system's captured step replayed on its own stream.  C(t) of the members the oracle file holds
     (tests/golden/make_batched_trajectories.py: those with v <= 125) after 3 steps, against
-    the oracle (FP64 and complex FP32 contractions)."""
+    the oracle (FP64 and complex FP32 contractions); every other member equal, bit for bit,
+    to its own run outside the batch."""
     import os
     path = os.path.join(os.path.dirname(__file__), "golden", "batched_trajectories.txt")
     d = np.loadtxt(path)
@@ -326,6 +327,15 @@ def test_batched_workload_members_against_oracle(prec, tol):
         worst = max(worst, err)
         print(f"member {k} (o={sh.o}, v={sh.v}): C(t) max abs err {err:.3e}", flush=True)
     batch.close()
+    # the members beyond the oracle's reach here: the batch equals each one's own run
+    for k, sh in enumerate(shapes):
+        if k in members:
+            continue
+        eps, chol = draw_system(sh, cfg=2, sys_id=k, chol_scale=(16.0 / sh.v) ** 0.5)
+        q = _prop(eps, chol, sh.o, sh.o, 0, 1, prec=prec, fixed_iters=2, fp_map=1, graph=True, max_steps=8)
+        q.step(0.025, 3)
+        assert np.array_equal(q.cumulant()[1], ps[k].cumulant()[1]), f"member {k}"
+        q.close()
     for p in ps:
         p.close()
     assert worst < tol

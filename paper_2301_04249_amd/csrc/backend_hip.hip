@@ -2082,10 +2082,20 @@ class HipBackend : public Backend {
     if (it != tuned_.end()) return it->second;
     if (!tuning_ || capturing_) {
       if (presplit && op.prec >= 2 && g.kchunk >= 1024) {
-        // split products (timed on the o=71, v=650 residual's shapes, sums of 2000
-        // and more): complex x complex and products with one short side run best on
-        // 128 x 128 tiles, the other mixed ones on 64 x 128
-        const int v = (ac && bc) || std::min(op.M, op.N) <= 8192 ? 3 : 1;
+        // split products (timed on the o=71, v=650 and o=95, v=561 residuals' shapes,
+        // sums of 2000 and more).  Complex x complex: 128 x 128 (one work-group per
+        // compute unit) unless its last round of tiles is mostly empty, where 64 x 64
+        // (two per compute unit, a round taking 1/1.76 as long) wins.  Mixed products:
+        // 128 x 128 with one short side or one very long one, else 64 x 128.
+        const int64_t units = op.batch > 1 ? op.batch : g.splitk;
+        int v;
+        if (ac && bc) {
+          const double r3 = std::ceil((double)((op.M + 127) / 128) * ((op.N + 127) / 128) * units / 256.0) * 1.76;
+          const double r0 = std::ceil((double)((op.M + 63) / 64) * ((op.N + 63) / 64) * units / 512.0);
+          v = r3 <= r0 ? 3 : 0;
+        } else {
+          v = std::min(op.M, op.N) <= 8192 || std::max(op.M, op.N) >= 131072 ? 3 : 1;
+        }
         if (split_tile_allowed(v, ac, bc)) return v;
       }
       int best = cand[0];

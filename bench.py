@@ -88,7 +88,10 @@ WORKLOADS = {
                       "evaluation plus one step, dt=0.01 au"),
     # Zn-porphyrin shape (655 orbitals: alpha 95/560, beta 94/561 with the hole), one
     # fixed-point pass per step (two amplitude sets), split-precision contractions
+    # (its CPU baseline is timed on the formaldehyde-shaped system: the spin-orbital oracle's
+    # integral blocks for all 95 occupied orbitals alone exceed a 64 GiB host)
     "zn": dict(shape=ZN_PORPHYRIN, cfg=5, dt=0.01, passes=1, steps=10, large=True, seed_amplitudes=1e-3,
+               cpu_sample="formaldehyde",
                desc="Zn-porphyrin-shaped core hole, o=95, v=560 per spin (beta hole: 95/94 occupied, 560/561 "
                     "virtual), Q=3000, L scaled by (16/v)^(1/2), amplitudes seeded N(0,1e-3), one fixed-point "
                     "pass per step, dt=0.01 au"),

@@ -88,7 +88,8 @@ typedef struct {
   uint32_t struct_size;    /* must be sizeof(rteom_options) */
   int32_t prec;            /* rteom_prec of the contractions; update and C(t) stay float64 */
   int32_t fp_map;          /* 0: plain fixed point of Eq. trapzrule; 1: diagonal ("denominator") map */
-  int32_t fp_fixed_iters;  /* > 0: exactly this many corrector passes per step (no convergence test) */
+  int32_t fp_fixed_iters;  /* > 0: exactly this many corrector passes per step (no convergence test);
+                              1 keeps no right-hand-side amplitude set */
   int32_t fp_max_iter;     /* pass limit when tolerance driven */
   double fp_tol;           /* max |T^(k+1) - T^(k)| over all amplitudes that ends the passes */
   int32_t dC_include_fT1;  /* 1: dC/dt includes sum f_ia t_ia (Eq. cum_gf3); 0: Eq. dcdt as printed */
@@ -103,7 +104,8 @@ typedef struct {
   int32_t tune;            /* 1: the first time a GEMM shape is met outside graph capture, each
                               candidate tile shape is timed on it and the fastest is kept for
                               the context (results are bit-identical for every tile shape);
-                              0: tile shape from a work-per-byte rule */
+                              0: tile shape from a rule (choices loaded with
+                              rteom_tile_cache_load are used first either way) */
   int32_t fp_anderson;     /* 0..8: history depth m of Anderson acceleration of the
                               tolerance-driven fixed point (fp_fixed_iters = 0) and of
                               rteom_ground_state: each pass mixes the last m results
@@ -128,9 +130,10 @@ typedef struct {
 void rteom_default_options(rteom_options* opt);
 
 /* Device bytes rteom_init needs for these sizes and options (no GPU work) under the
-   memory plan it would choose: three amplitude sets (plus T_n for tolerance-driven
-   steps and the Anderson history), the Cholesky vectors and resident integral blocks,
-   and the scratch of one residual evaluation.  OOM if no plan fits mem_limit. */
+   memory plan it would choose: three amplitude sets (two with fp_fixed_iters = 1; plus
+   T_n for tolerance-driven steps and the Anderson history), the Cholesky vectors and
+   resident integral blocks, and the scratch of one residual evaluation.  OOM if no plan
+   fits mem_limit. */
 rteom_status rteom_workspace_query(int32_t n_orb, int32_t n_occ_a, int32_t n_occ_b,
                                    int32_t n_chol, int32_t core_orb, int32_t core_spin,
                                    const rteom_options* opt, size_t* bytes);

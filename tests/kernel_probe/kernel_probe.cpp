@@ -113,9 +113,8 @@ static int check(Backend* be) {
   return fails;
 }
 
-// Timing of each tile shape: (M, N, K, a complex, b complex, a k-contiguous, b
-// k-contiguous, largest split-K factor tried); operands hold only their real planes
-// when real.
+// Permute check: 4-d index orders, real and complex input and output, with and
+// without beta, against host loops.
 static int check_permute(Backend* be) {
   int fails = 0, runs = 0;
   srand(7);

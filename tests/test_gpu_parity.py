@@ -459,14 +459,14 @@ def test_formaldehyde_1000_steps():
     """The formaldehyde-shaped run of 1000 steps (25 au), 2 passes per step with the diagonal
     (denominator) fixed-point map: two plain passes per step lose stability after ~300 steps
     at this dt, the denominator map stays bounded.  The FP64 device trajectory against the
-    oracle's over the 30 steps the oracle file holds (tests/golden/make_formaldehyde_trajectory.py
+    oracle's over the 150 steps the oracle file holds (tests/golden/make_formaldehyde_trajectory.py
     --fp-map denominator), then float32, bf16x3 and fp16x3 contractions against that FP64
     trajectory over all 1000 steps: C(t) max abs error at most 1e-5 of max |C| and the QP peak
     within 1e-4 eV.  (The oracle's 1000 steps would take about twelve hours on eight host
     cores; the FP64 device path stands in for it beyond, pinned by its agreement there and by
     the 200-step plain-map trajectory.)"""
     import os
-    path = os.path.join(os.path.dirname(__file__), "golden", "formaldehyde_denominator_30.txt")
+    path = os.path.join(os.path.dirname(__file__), "golden", "formaldehyde_denominator.txt")
     d = np.loadtxt(path)
     c_ref = d[:, 1] + 1j * d[:, 2]
     eps, chol = draw_system(FORMALDEHYDE, cfg=1, chol_scale=(16.0 / FORMALDEHYDE.v) ** 0.5)
